@@ -1,0 +1,64 @@
+"""Pins of the oracle's refinement and GMRES drivers (Sec. 5.2: the DDM as
+preconditioner of GMRES, stopped on the relative residual).  Both must reach
+the global PML solution, the fixed point that the DDM only approximates, and
+GMRES must take few iterations, as the paper reports (3-4 steps to 1e-6 in
+constant media, 6-7 for a heterogeneous model)."""
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from paper_2003_02585_amd import workloads as wl
+
+
+def _setup(layer=None, N=64, P=(4, 4)):
+    h = 1.0 / N
+    k = 2 * np.pi / (10 * h)
+    kap = wl.constant_kappa((N, N), k) if layer is None else \
+        wl.two_layer_kappa((N, N), h, k, layer * k, 0.37)
+    prob = O.Problem(kap, h, 16)
+    part = O.Partition(prob, P)
+    sol = O.SubdomainSolvers(part)
+    S = O.global_operator(prob)
+    f = wl.gaussian_source((N, N), h, (0.31, 0.77), 2 * h) + \
+        wl.gaussian_source((N, N), h, (0.6, 0.2), 2 * h)
+    b = O.global_rhs(prob, f)
+    return prob, part, sol, S, b
+
+
+def _precond(prob, part, sol, rounds):
+    def M(r):
+        return O.ddm_apply(prob, part, r.reshape(prob.gshape), rounds=rounds,
+                           solvers=sol).ravel()
+    return M
+
+
+def test_refinement_reaches_global_solution():
+    prob, part, sol, S, b = _setup()
+    ug = spla.splu(S.tocsc()).solve(b.ravel())
+    x, hist = O.refine(S, b, _precond(prob, part, sol, 1), tol=1e-12, maxit=10)
+    assert hist[-1] <= 1e-12 and len(hist) <= 5, hist
+    # residual reduction per step is of the order of the DDM's layer error
+    assert hist[1] < 1e-3
+    assert np.linalg.norm(x - ug) / np.linalg.norm(ug) < 1e-10
+
+
+def test_gmres_two_layer_matches_direct_solve():
+    prob, part, sol, S, b = _setup(layer=1.5)
+    ug = spla.splu(S.tocsc()).solve(b.ravel())
+    for rounds, max_it in ((1, 8), (2, 4)):
+        x, hist = O.gmres(S, b, _precond(prob, part, sol, rounds), m=20,
+                          tol=1e-10, maxit=30)
+        assert hist[-1] <= 1e-10, hist
+        assert np.linalg.norm(x - ug) / np.linalg.norm(ug) < 1e-8
+    # GMRES on the unpreconditioned system is far slower (sanity of M)
+    x0, h0 = O.gmres(S, b, lambda r: r, m=20, tol=1e-6, maxit=40)
+    assert h0[-1] > 1e-6
+
+
+def test_gmres_identity_preconditioner_small_dense():
+    # GMRES itself against a dense solve on a tiny system
+    prob, part, sol, S, b = _setup(N=16, P=(2, 2))
+    x, hist = O.gmres(S, b, lambda r: r, m=30, tol=1e-12, maxit=2000)
+    ref = np.linalg.solve(S.toarray(), b.ravel())
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
