@@ -1,0 +1,176 @@
+/*
+ * hdsw -- trace-transfer diagonal sweeping DDM for the Helmholtz equation
+ * with PML, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Leng & Ju, "Trace transfer-based diagonal sweeping DDM for the
+ * Helmholtz equation: algorithms and convergence analysis",
+ * arXiv:2003.02585 -- Algorithm 2.1 (2D), Algorithm 4.1 (3D), used as a
+ * preconditioner of an FP64 Krylov iteration as in Sec. 5.2.
+ *
+ * Problem (Sec. 2.1, eq. (helm), (radiation), (PML)): Delta u + k(x)^2 u = f
+ * in R^d with the radiation condition, replaced by a uniaxial PML outside
+ * the box B = [0, n_x h] x [0, n_y h] (x [0, n_z h]).  The library
+ * discretizes eq. (PML) with the second-order 5-point (2D) / 7-point (3D)
+ * stencil on cell-centred nodes x_p = (p + 1/2) h, W layer nodes per side,
+ * quadratic profile sigma(t) = sigma0 (t / (W h))^2, alpha = 1 + i sigma,
+ * sigma0 = 3 ln(1/pml_R) / (min k * W h), Dirichlet ghosts beyond the layer.
+ * The J-scaled discrete operator S is complex symmetric.  The layer's
+ * wavenumber is that of the nearest interior node (eq. (wave_number)).
+ *
+ * Partition (Sec. 2.3 / Sec. 4): nsub[a] equal boxes per axis; each
+ * subdomain is extended by its own W-node PML and its wavenumber by the
+ * nearest point of the subdomain.
+ *
+ * Conventions for every entry point:
+ *  - All arrays are C order with x the fastest index.  Interior grids are
+ *    [n_z][n_y][n_x]; "global" grids (interior plus layer) are
+ *    [M_z][M_y][M_x] with M_a = n_a + 2 W.  Batches of right-hand sides are
+ *    the slowest index: [nrhs][grid].
+ *  - Device pointers must come from hipMalloc (or a caching allocator on
+ *    top of it) on the context's device; they stay owned by the caller and
+ *    must stay valid until the call returns.
+ *  - Every call is ordered on the context's stream and returns when its
+ *    work is complete.  One host thread per context; separate contexts may
+ *    be used concurrently on separate streams.
+ *  - Nothing throws or aborts across this interface; every function that
+ *    can fail returns an hdsw_status.  HDSW_EDEVICE is sticky: the context
+ *    must be destroyed.
+ */
+#ifndef HDSW_H
+#define HDSW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdsw_ctx hdsw_ctx;
+
+typedef struct { double re, im; } hdsw_c128;
+
+typedef enum {
+  HDSW_OK = 0,
+  HDSW_EINVAL = 1,        /* invalid argument (shape, value, pointer)          */
+  HDSW_ENOMEM = 2,        /* device allocation or HBM budget exceeded          */
+  HDSW_EDEVICE = 3,       /* HIP runtime error (sticky)                        */
+  HDSW_ENOTFACTORED = 4,  /* solve / apply before hdsw_factor                  */
+  HDSW_ENOCONV = 5,       /* iteration limit reached; last iterate returned    */
+  HDSW_EBUSY = 6          /* context in use                                     */
+} hdsw_status;
+
+enum { HDSW_FP64 = 0, HDSW_MIXED = 1 };
+
+typedef struct {
+  int dim;        /* 2 or 3                                                  */
+  int n[3];       /* interior nodes per axis (x, y, z); n[2] ignored in 2D    */
+  double h;       /* mesh width; B = [0, n[a] h] per axis                     */
+} hdsw_grid;
+
+typedef struct {
+  int nsub[3];    /* subdomains per axis; n[a] % nsub[a] == 0              */
+} hdsw_partition;
+
+typedef struct {
+  int precision;  /* HDSW_FP64: factors and sweeps in complex128.
+                     HDSW_MIXED: factors and sweeps in complex64; the global
+                     residual, the update and the Krylov iteration in FP64 */
+  int rounds;     /* rounds of the 2^d sweeps per DDM application (>= 1);
+                     2 = one extra round (Thm 3.10, Sec. 4)                  */
+  double pml_R;   /* nominal layer attenuation giving sigma0 (> 0, < 1)      */
+  double tol;     /* stop when ||b - S x||_2 / ||b||_2 <= tol, per RHS       */
+  int max_iter;   /* iteration limit of hdsw_solve                           */
+  int gmres_m;    /* 0: iterative refinement x += M^{-1}(b - S x);
+                     m > 0: right-preconditioned GMRES(m), FP64 Arnoldi     */
+  int dedup;      /* share factors between identical subdomain operators    */
+  size_t hbm_budget; /* bytes for factors plus workspaces; 0 = no limit      */
+} hdsw_options;
+
+typedef struct {
+  int iters;            /* iterations until this RHS met tol (or max_iter)  */
+  double rel_residual;  /* final ||b - S x|| / ||b|| in FP64                */
+} hdsw_solve_info;
+
+/* Fills *opt with the defaults: HDSW_MIXED, rounds 1, pml_R 1e-4,
+ * tol 1e-10, max_iter 30, gmres_m 0, dedup 1, no budget. */
+void hdsw_default_options(hdsw_options* opt);
+
+/* Validates the problem, builds the partition, the per-subdomain layer
+ * profiles and wavenumbers (eq. (sigma), eq. (wave_number)), the sweep
+ * schedule (eq. (Sorder2D)/(Sorder3D), eq. (step_subd)/(step_subd3)) and the
+ * trace routing (Rules 2.4/2.5, 4.1/4.2 applied over rounds * 2^d sweeps),
+ * groups identical subdomain operators when opt->dedup, and allocates all
+ * device state on the current device.
+ *   kappa_host : host array [n_z][n_y][n_x] of real k > 0, finite; copied.
+ *   pml_width  : W >= 1 layer nodes per side (global and subdomain layers).
+ *   stream     : hipStream_t to order all work on (NULL = default stream).
+ *   out        : receives the context; unchanged on failure.
+ * Errors: EINVAL (dim not 2/3, n % nsub != 0, nonpositive sizes, W < 1,
+ * non-finite or nonpositive k, h <= 0, bad options, NULL pointers), ENOMEM
+ * (budget or allocation), EDEVICE. */
+hdsw_status hdsw_setup(const hdsw_grid* grid, const double* kappa_host,
+                       const hdsw_partition* part, int pml_width,
+                       const hdsw_options* opt, void* stream, hdsw_ctx** out);
+
+/* Factors every distinct subdomain operator once (the paper factors each
+ * subdomain problem once with a sparse direct solver, Sec. 5): block
+ * tridiagonal LU over grid lines (2D) or planes (3D),
+ *   D_1 = A_1,  D_k = A_k - B_k D_{k-1}^{-1} B_k,  X_k = D_k^{-1},
+ * each D_k inverted by Gauss-Jordan elimination with partial pivoting, and
+ * (2D) the interface-to-interface response of each subdomain operator.
+ * Idempotent.  Errors: EDEVICE, ENOMEM. */
+hdsw_status hdsw_factor(hdsw_ctx* ctx);
+
+/* Solves S x = b, b = h^2 J f, for nrhs sources:
+ *   f_dev : device complex128 [nrhs][n_z][n_y][n_x], source on the interior
+ *           nodes of B (zero in the layer, f supported in B, Sec. 2.1).
+ *   x_dev : device complex128 [nrhs][n_z][n_y][n_x], receives u on the
+ *           interior nodes.
+ *   info  : host array of nrhs entries, or NULL.
+ * Iterates (refinement or GMRES(m), FP64 residual on the device) with the
+ * DDM of Algorithm 2.1 / 4.1 as preconditioner until every RHS meets tol.
+ * Errors: EINVAL, ENOTFACTORED, ENOCONV (x holds the last iterate, info the
+ * residuals), ENOMEM (nrhs too large for the budget), EDEVICE. */
+hdsw_status hdsw_solve(hdsw_ctx* ctx, const hdsw_c128* f_dev,
+                       hdsw_c128* x_dev, int nrhs, hdsw_solve_info* info);
+
+/* One application of the DDM (opts.rounds rounds of Algorithm 2.1 / 4.1)
+ * to global-grid right-hand sides:
+ *   r_dev : device complex128 [nrhs][M_z][M_y][M_x], the b-space vector
+ *           (for example a residual b - S x; nonzero in the layer allowed).
+ *   z_dev : device complex128 [nrhs][M_z][M_y][M_x], receives u_DDM (sum of
+ *           the local solutions on owned nodes, Algorithm 2.1's last line).
+ * Computes in complex64 when precision == HDSW_MIXED.
+ * Errors: EINVAL, ENOTFACTORED, ENOMEM, EDEVICE. */
+hdsw_status hdsw_apply_precond(hdsw_ctx* ctx, const hdsw_c128* r_dev,
+                               hdsw_c128* z_dev, int nrhs);
+
+/* Global residual r = b - S x on the global grid in FP64 (b on the global
+ * grid, both [nrhs][M_z][M_y][M_x] complex128 on the device), and per-RHS
+ * norms ||r||_2 written to rnorm_host (nrhs doubles, may be NULL). */
+hdsw_status hdsw_residual(hdsw_ctx* ctx, const hdsw_c128* b_dev,
+                          const hdsw_c128* x_dev, hdsw_c128* r_dev, int nrhs,
+                          double* rnorm_host);
+
+/* Sizes: factor bytes, number of distinct subdomain operators, workspace
+ * bytes currently allocated; any pointer may be NULL. */
+hdsw_status hdsw_query(const hdsw_ctx* ctx, size_t* factor_bytes,
+                       int* n_distinct_ops, size_t* workspace_bytes);
+
+/* Kernel timing: when enabled, HIP events bracket every launch of kernel
+ * class `which` (0 = batched block solve, 1 = sweep-step interface GEMM,
+ * 2 = block factorization, 3 = FP64 residual) on the context's stream.
+ * hdsw_timing_get returns the accumulated milliseconds, launch count and
+ * the algorithmic flops and bytes of those launches, then resets them. */
+hdsw_status hdsw_timing_enable(hdsw_ctx* ctx, int enable);
+hdsw_status hdsw_timing_get(hdsw_ctx* ctx, int which, double* total_ms,
+                            long long* launches, double* flops, double* bytes);
+
+void hdsw_destroy(hdsw_ctx* ctx);
+const char* hdsw_status_str(hdsw_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDSW_H */

@@ -1,0 +1,130 @@
+// extern "C" entry points of libhdsw (declared in include/hdsw.h).  Argument
+// marshalling and error mapping only; the work is in driver.cpp / krylov.cpp
+// and the kernels.
+#include <new>
+
+#include "hdsw_internal.hpp"
+
+namespace hdsw {
+hdsw_status setup_impl(const hdsw_grid*, const double*, const hdsw_partition*, int,
+                       const hdsw_options*, void*, hdsw_ctx**);
+hdsw_status factor(hdsw_ctx*);
+hdsw_status solve(hdsw_ctx*, const c128*, c128*, int, hdsw_solve_info*);
+hdsw_status apply_precond(hdsw_ctx*, const c128*, c128*, int);
+hdsw_status residual(hdsw_ctx*, const c128*, const c128*, c128*, int, double*);
+hdsw_status timing_get(hdsw_ctx*, int, double*, long long*, double*, double*);
+void destroy(hdsw_ctx*);
+}  // namespace hdsw
+
+extern "C" {
+
+void hdsw_default_options(hdsw_options* o) {
+  if (!o) return;
+  o->precision = HDSW_MIXED;
+  o->rounds = 1;
+  o->pml_R = 1e-4;
+  o->tol = 1e-10;
+  o->max_iter = 30;
+  o->gmres_m = 0;
+  o->dedup = 1;
+  o->hbm_budget = 0;
+}
+
+hdsw_status hdsw_setup(const hdsw_grid* grid, const double* kappa_host,
+                       const hdsw_partition* part, int pml_width, const hdsw_options* opt,
+                       void* stream, hdsw_ctx** out) {
+  try {
+    return hdsw::setup_impl(grid, kappa_host, part, pml_width, opt, stream, out);
+  } catch (const std::bad_alloc&) {
+    return HDSW_ENOMEM;
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_factor(hdsw_ctx* ctx) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::factor(ctx);
+  } catch (const std::bad_alloc&) {
+    return HDSW_ENOMEM;
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_solve(hdsw_ctx* ctx, const hdsw_c128* f, hdsw_c128* x, int nrhs,
+                       hdsw_solve_info* info) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::solve(ctx, reinterpret_cast<const hdsw::c128*>(f),
+                       reinterpret_cast<hdsw::c128*>(x), nrhs, info);
+  } catch (const std::bad_alloc&) {
+    return HDSW_ENOMEM;
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_apply_precond(hdsw_ctx* ctx, const hdsw_c128* r, hdsw_c128* z, int nrhs) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::apply_precond(ctx, reinterpret_cast<const hdsw::c128*>(r),
+                               reinterpret_cast<hdsw::c128*>(z), nrhs);
+  } catch (const std::bad_alloc&) {
+    return HDSW_ENOMEM;
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_residual(hdsw_ctx* ctx, const hdsw_c128* b, const hdsw_c128* x,
+                          hdsw_c128* r, int nrhs, double* rnorm) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::residual(ctx, reinterpret_cast<const hdsw::c128*>(b),
+                          reinterpret_cast<const hdsw::c128*>(x),
+                          reinterpret_cast<hdsw::c128*>(r), nrhs, rnorm);
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_query(const hdsw_ctx* ctx, size_t* factor_bytes, int* n_distinct_ops,
+                       size_t* workspace_bytes) {
+  if (!ctx) return HDSW_EINVAL;
+  if (factor_bytes) *factor_bytes = ctx->factor_bytes;
+  if (n_distinct_ops) *n_distinct_ops = ctx->nops;
+  if (workspace_bytes)
+    *workspace_bytes = ctx->alloc_bytes > ctx->factor_bytes ? ctx->alloc_bytes - ctx->factor_bytes : 0;
+  return HDSW_OK;
+}
+
+hdsw_status hdsw_timing_enable(hdsw_ctx* ctx, int enable) {
+  if (!ctx) return HDSW_EINVAL;
+  ctx->tm.on = enable != 0;
+  return HDSW_OK;
+}
+
+hdsw_status hdsw_timing_get(hdsw_ctx* ctx, int which, double* total_ms, long long* launches,
+                            double* flops, double* bytes) {
+  if (!ctx) return HDSW_EINVAL;
+  return hdsw::timing_get(ctx, which, total_ms, launches, flops, bytes);
+}
+
+void hdsw_destroy(hdsw_ctx* ctx) { hdsw::destroy(ctx); }
+
+const char* hdsw_status_str(hdsw_status s) {
+  switch (s) {
+    case HDSW_OK: return "HDSW_OK";
+    case HDSW_EINVAL: return "HDSW_EINVAL: invalid argument";
+    case HDSW_ENOMEM: return "HDSW_ENOMEM: device memory or HBM budget exhausted";
+    case HDSW_EDEVICE: return "HDSW_EDEVICE: HIP runtime error (context unusable)";
+    case HDSW_ENOTFACTORED: return "HDSW_ENOTFACTORED: call hdsw_factor first";
+    case HDSW_ENOCONV: return "HDSW_ENOCONV: iteration limit reached";
+    case HDSW_EBUSY: return "HDSW_EBUSY: context in use";
+  }
+  return "HDSW: unknown status";
+}
+
+}  // extern "C"

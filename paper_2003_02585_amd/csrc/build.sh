@@ -1,0 +1,20 @@
+#!/bin/bash
+# Builds libhdsw.so for gfx950 next to this script's package directory.
+set -euo pipefail
+here="$(cd "$(dirname "$0")" && pwd)"
+out="${here}/../libhdsw.so"
+flags=(-O3 -std=c++17 -fPIC --offload-arch=gfx950
+       -Xclang -target-feature -Xclang -packed-fp32-ops
+       -Wall -Wno-unused-result)
+objs=()
+tmp="$(mktemp -d)"
+trap 'rm -rf "$tmp"' EXIT
+for src in kernels.hip driver.cpp krylov.cpp api.cpp; do
+  o="${tmp}/${src%.*}.o"
+  hipcc "${flags[@]}" -x hip -c "${here}/${src}" -o "$o" &
+  objs+=("$o")
+done
+wait
+hipcc --offload-arch=gfx950 -shared -fPIC "${objs[@]}" -o "${out}.tmp"
+mv "${out}.tmp" "$out"
+echo "built $out"

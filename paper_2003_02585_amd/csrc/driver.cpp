@@ -1,0 +1,738 @@
+// Host runtime of the hdsw library: validation, partition, sweep schedule and
+// trace routing, operator deduplication, device memory, factorization, the
+// DDM application (Algorithm 2.1) and the FP64 refinement / GMRES drivers.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <unordered_map>
+
+#include "hdsw_internal.hpp"
+
+namespace hdsw {
+
+#define HCHK(expr)                                   \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) {                          \
+      c->sticky = HDSW_EDEVICE;                      \
+      return HDSW_EDEVICE;                           \
+    }                                                \
+  } while (0)
+
+// ------------------------------------------------------------ schedule
+// Sweep order: eq. (Sorder2D) / (Sorder3D).
+static void sweep_dirs(int dim, std::vector<std::array<int, 3>>& out) {
+  out.clear();
+  if (dim == 2) {
+    out.push_back({1, 1, 0});
+    out.push_back({-1, 1, 0});
+    out.push_back({1, -1, 0});
+    out.push_back({-1, -1, 0});
+  } else {
+    for (int dz : {1, -1})
+      for (int dy : {1, -1})
+        for (int dx : {1, -1}) out.push_back({dx, dy, dz});
+  }
+}
+
+// Rule 2.4 / 4.1: similar directions
+static bool similar(const int* e, const int* d, int dim) {
+  int dot = 0;
+  for (int a = 0; a < dim; ++a) dot += e[a] * d[a];
+  if (dot <= 0) return false;
+  if (dim == 3)
+    for (int a = 0; a < 3; ++a)
+      if (e[a] * d[a] < 0) return false;
+  return true;
+}
+
+// Rule 2.5 / 4.2: may a trace of direction e generated in a sweep dg be used
+// in the later sweep du?
+static bool opposite_blocked(const int* e, const int* dg, const int* du, int dim) {
+  if (dim == 2) return du[0] == -dg[0] && du[1] == -dg[1];
+  static const int planes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (auto& pl : planes) {
+    int a = pl[0], b = pl[1];
+    int zeros = (e[a] == 0) + (e[b] == 0);
+    if (zeros != 1) continue;
+    if (du[a] == -dg[a] && du[b] == -dg[b]) return true;
+  }
+  return false;
+}
+
+static void build_schedule(hdsw_ctx* c) {
+  Geometry& g = c->g;
+  Schedule& s = c->sch;
+  std::vector<std::array<int, 3>> base;
+  sweep_dirs(g.dim, base);
+  int per = (int)base.size();
+  s.nsweeps = c->opt.rounds * per;
+  s.dir.resize(s.nsweeps);
+  for (int L = 0; L < s.nsweeps; ++L) s.dir[L] = base[L % per];
+  s.nsteps = 1;
+  for (int a = 0; a < g.dim; ++a) s.nsteps += g.P[a] - 1;
+  s.step_off.assign(s.nsweeps * s.nsteps, 0);
+  s.step_cnt.assign(s.nsweeps * s.nsteps, 0);
+  s.step_subs.clear();
+  for (int L = 0; L < s.nsweeps; ++L) {
+    const auto& d = s.dir[L];
+    std::vector<std::vector<int>> groups(s.nsteps);
+    for (int sub = 0; sub < g.nsub; ++sub) {
+      int cc[3];
+      g.sub_coords(sub, cc);
+      int st = 0;  // 0-based step: sum of ihat (eq. step_subd_ij / step_subd_k)
+      for (int a = 0; a < g.dim; ++a) st += d[a] == 1 ? cc[a] : g.P[a] - 1 - cc[a];
+      groups[st].push_back(sub);
+    }
+    for (int st = 0; st < s.nsteps; ++st) {
+      s.step_off[L * s.nsteps + st] = (int)s.step_subs.size();
+      s.step_cnt[L * s.nsteps + st] = (int)groups[st].size();
+      s.step_subs.insert(s.step_subs.end(), groups[st].begin(), groups[st].end());
+    }
+  }
+  // routing: smallest l' >= L allowed by the rules over the extended list
+  s.lprime.assign(s.nsweeps * 6, -1);
+  for (int L = 0; L < s.nsweeps; ++L) {
+    for (int f = 0; f < 2 * g.dim; ++f) {
+      int e[3] = {0, 0, 0};
+      e[f >> 1] = (f & 1) ? 1 : -1;
+      for (int lp = L; lp < s.nsweeps; ++lp) {
+        if (!similar(e, s.dir[lp].data(), g.dim)) continue;
+        if (lp > L && opposite_blocked(e, s.dir[L].data(), s.dir[lp].data(), g.dim))
+          continue;
+        s.lprime[L * 6 + f] = lp;
+        break;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ PML profile
+// alpha = 1 + i sigma0 (dist / W)^2, dist = distance outside the box in
+// units of h (quadratic profile of eq. (sigma), translation invariant).
+static c128 alpha_of(double dist, double s0, int W) {
+  double t = dist / W;
+  return mk<double>(1.0, s0 * t * t);
+}
+// node p (local 0..ne-1) and half-point q (0..ne) of a box of na interior
+// nodes preceded and followed by W layer nodes
+static double node_dist(int p, int W, int na) {
+  if (p < W) return W - p - 0.5;
+  if (p >= W + na) return p - (W + na) + 0.5;
+  return 0.0;
+}
+static double half_dist(int q, int W, int na) {
+  if (q < W) return double(W - q);
+  if (q > W + na) return double(q - W - na);
+  return 0.0;
+}
+
+static uint64_t fnv1a(const void* data, size_t n) {
+  const unsigned char* p = (const unsigned char*)data;
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// ------------------------------------------------------------ memory
+static hdsw_status dev_alloc(hdsw_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (c->opt.hbm_budget && c->alloc_bytes + bytes > c->opt.hbm_budget) return HDSW_ENOMEM;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return HDSW_ENOMEM;
+  }
+  c->alloc_bytes += bytes;
+  c->bufs.push_back({*p, bytes});
+  return HDSW_OK;
+}
+static void dev_free(hdsw_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->bufs.size(); ++i) {
+    if (c->bufs[i].p == p) {
+      c->alloc_bytes -= c->bufs[i].bytes;
+      (void)hipFree(p);
+      c->bufs.erase(c->bufs.begin() + i);
+      return;
+    }
+  }
+}
+#define ACHK(expr)                         \
+  do {                                     \
+    hdsw_status s_ = (expr);               \
+    if (s_ != HDSW_OK) return s_;          \
+  } while (0)
+
+static size_t elt(const hdsw_ctx* c) {
+  return c->opt.precision == HDSW_MIXED ? sizeof(c64) : sizeof(c128);
+}
+
+// ------------------------------------------------------------ timing
+struct PendingEv {
+  int cls;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+static std::unordered_map<const hdsw_ctx*, std::vector<PendingEv>>& pending() {
+  static std::unordered_map<const hdsw_ctx*, std::vector<PendingEv>> m;
+  return m;
+}
+struct TimedScope {
+  hdsw_ctx* c;
+  int cls;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  TimedScope(hdsw_ctx* c_, int cls_, double f, double b) : c(c_), cls(cls_), flops(f), bytes(b) {
+    if (c->tm.on) {
+      if (hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, c->stream);
+      else a = nullptr;
+    }
+  }
+  ~TimedScope() {
+    if (c->tm.on && a) {
+      hipEvent_t b = nullptr;
+      if (hipEventCreate(&b) == hipSuccess) {
+        (void)hipEventRecord(b, c->stream);
+        pending()[c].push_back({cls, a, b, flops, bytes});
+      } else {
+        (void)hipEventDestroy(a);
+      }
+    }
+  }
+};
+
+static void resolve_timing(hdsw_ctx* c) {
+  auto& v = pending()[c];
+  for (auto& e : v) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      c->tm.ms[e.cls] += ms;
+      c->tm.launches[e.cls] += 1;
+      c->tm.flops[e.cls] += e.flops;
+      c->tm.bytes[e.cls] += e.bytes;
+    }
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  v.clear();
+}
+
+// ------------------------------------------------------------ setup
+hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_partition* part,
+                       int W, const hdsw_options* opt, void* stream, hdsw_ctx** out) {
+  if (!grid || !kappa || !part || !opt || !out) return HDSW_EINVAL;
+  if (grid->dim != 2) return HDSW_EINVAL;  // 3D sweeps are not built
+  if (!(grid->h > 0) || !std::isfinite(grid->h) || W < 1) return HDSW_EINVAL;
+  if (opt->precision != HDSW_FP64 && opt->precision != HDSW_MIXED) return HDSW_EINVAL;
+  if (opt->rounds < 1 || opt->rounds > 4 || !(opt->pml_R > 0 && opt->pml_R < 1) ||
+      !(opt->tol > 0) || opt->max_iter < 0 || opt->gmres_m < 0 || opt->gmres_m > 200)
+    return HDSW_EINVAL;
+  hdsw_ctx* c = new (std::nothrow) hdsw_ctx();
+  if (!c) return HDSW_ENOMEM;
+  Geometry& g = c->g;
+  g.dim = grid->dim;
+  g.W = W;
+  g.h = grid->h;
+  long long nint = 1;
+  for (int a = 0; a < g.dim; ++a) {
+    g.N[a] = grid->n[a];
+    g.P[a] = part->nsub[a];
+    if (g.N[a] < 1 || g.P[a] < 1 || g.N[a] % g.P[a] != 0 || g.N[a] / g.P[a] < 2) {
+      delete c;
+      return HDSW_EINVAL;
+    }
+    g.na[a] = g.N[a] / g.P[a];
+    g.ne[a] = g.na[a] + 2 * W;
+    g.M[a] = g.N[a] + 2 * W;
+    nint *= g.N[a];
+  }
+  g.nsub = 1;
+  g.sub_nodes = 1;
+  g.glob_nodes = 1;
+  for (int a = 0; a < g.dim; ++a) {
+    g.nsub *= g.P[a];
+    g.sub_nodes *= g.ne[a];
+    g.glob_nodes *= g.M[a];
+  }
+  g.int_nodes = nint;
+  g.n = g.ne[0];
+  g.K = g.ne[1];
+  if (g.n > 512) {  // one x-line per block; the block solver keeps a row per lane
+    delete c;
+    return HDSW_EINVAL;
+  }
+  g.nsides = 2 * g.dim;
+  g.side_len[0] = g.side_len[1] = g.ne[1];
+  g.side_len[2] = g.side_len[3] = g.ne[0];
+  int off = 0;
+  for (int s = 0; s < g.nsides; ++s) {
+    g.side_off[s] = off;
+    off += 2 * g.side_len[s];
+  }
+  g.NI = off;
+  double kmin = 1e300;
+  for (long long i = 0; i < nint; ++i) {
+    double k = kappa[i];
+    if (!std::isfinite(k) || !(k > 0)) {
+      delete c;
+      return HDSW_EINVAL;
+    }
+    kmin = std::min(kmin, k);
+  }
+  c->opt = *opt;
+  g.s0 = 3.0 * std::log(1.0 / opt->pml_R) / (kmin * W * g.h);
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return HDSW_EDEVICE;
+  }
+  c->kappa.assign(kappa, kappa + nint);
+
+  GeoDev& d = c->gd;
+  d.dim = g.dim;
+  d.W = g.W;
+  d.n = g.n;
+  d.K = g.K;
+  d.NI = g.NI;
+  d.nsub = g.nsub;
+  for (int a = 0; a < 3; ++a) {
+    d.N[a] = g.N[a];
+    d.P[a] = g.P[a];
+    d.na[a] = g.na[a];
+    d.ne[a] = g.ne[a];
+    d.M[a] = g.M[a];
+  }
+  for (int s = 0; s < 6; ++s) {
+    d.side_len[s] = g.side_len[s];
+    d.side_off[s] = g.side_off[s];
+  }
+
+  build_schedule(c);
+
+  // extended wavenumber of each subdomain (eq. wave_number: nearest point
+  // of the subdomain = index clamping) and deduplication by exact bytes
+  std::vector<std::vector<double>> kops;
+  std::unordered_map<uint64_t, std::vector<int>> byhash;
+  c->op_of_sub.assign(g.nsub, -1);
+  std::vector<double> ks((size_t)g.sub_nodes);
+  for (int s = 0; s < g.nsub; ++s) {
+    int cc[3];
+    g.sub_coords(s, cc);
+    for (int k = 0; k < g.ne[1]; ++k) {
+      int iy = std::min(std::max(cc[1] * g.na[1] + k - W, cc[1] * g.na[1]),
+                        (cc[1] + 1) * g.na[1] - 1);
+      for (int p = 0; p < g.ne[0]; ++p) {
+        int ix = std::min(std::max(cc[0] * g.na[0] + p - W, cc[0] * g.na[0]),
+                          (cc[0] + 1) * g.na[0] - 1);
+        ks[(size_t)k * g.ne[0] + p] = c->kappa[(size_t)iy * g.N[0] + ix];
+      }
+    }
+    int op = -1;
+    if (opt->dedup) {
+      uint64_t hsh = fnv1a(ks.data(), ks.size() * sizeof(double));
+      for (int cand : byhash[hsh])
+        if (std::memcmp(kops[cand].data(), ks.data(), ks.size() * sizeof(double)) == 0) {
+          op = cand;
+          break;
+        }
+      if (op < 0) {
+        op = (int)kops.size();
+        kops.push_back(ks);
+        byhash[hsh].push_back(op);
+        c->rep_of_op.push_back(s);
+      }
+    } else {
+      op = (int)kops.size();
+      kops.push_back(ks);
+      c->rep_of_op.push_back(s);
+    }
+    c->op_of_sub[s] = op;
+  }
+  c->nops = (int)kops.size();
+
+  // alpha tables: subdomain-local and global, node and half-points per axis
+  std::vector<c128> al_sub, al_glob;
+  for (int a = 0; a < g.dim; ++a) {
+    c->alpha_sub_off[2 * a] = (int)al_sub.size();
+    for (int p = 0; p < g.ne[a]; ++p) al_sub.push_back(alpha_of(node_dist(p, W, g.na[a]), g.s0, W));
+    c->alpha_sub_off[2 * a + 1] = (int)al_sub.size();
+    for (int q = 0; q <= g.ne[a]; ++q) al_sub.push_back(alpha_of(half_dist(q, W, g.na[a]), g.s0, W));
+    c->alpha_glob_off[2 * a] = (int)al_glob.size();
+    for (int p = 0; p < g.M[a]; ++p) al_glob.push_back(alpha_of(node_dist(p, W, g.N[a]), g.s0, W));
+    c->alpha_glob_off[2 * a + 1] = (int)al_glob.size();
+    for (int q = 0; q <= g.M[a]; ++q) al_glob.push_back(alpha_of(half_dist(q, W, g.N[a]), g.s0, W));
+  }
+
+  auto fail = [&](hdsw_status st) {
+    for (auto& b : c->bufs) (void)hipFree(b.p);
+    delete c;
+    return st;
+  };
+  hdsw_status st;
+  size_t e = elt(c);
+  c->coef_stride = (size_t)g.K * (g.n + 1) + (size_t)(g.K + 1) * g.n + (size_t)g.K * g.n;
+  size_t xbytes = (size_t)c->nops * g.K * g.n * g.n * e;
+  size_t tbytes = (size_t)c->nops * g.NI * g.NI * e;
+  c->factor_bytes = xbytes + tbytes;
+  void* p;
+#define SALLOC(dst, bytes)                     \
+  do {                                         \
+    st = dev_alloc(c, &p, (bytes));            \
+    if (st != HDSW_OK) return fail(st);        \
+    dst = decltype(dst)(p);                    \
+  } while (0)
+  SALLOC(c->d_X, xbytes);
+  SALLOC(c->d_T, tbytes);
+  SALLOC(c->d_coef, c->coef_stride * c->nops * sizeof(c128));
+  SALLOC(c->d_coefT, c->coef_stride * c->nops * e);
+  SALLOC(c->d_kappa_sub, (size_t)c->nops * g.sub_nodes * sizeof(double));
+  SALLOC(c->d_kappa, (size_t)nint * sizeof(double));
+  SALLOC(c->d_alpha_sub, al_sub.size() * sizeof(c128));
+  SALLOC(c->d_alpha_glob, al_glob.size() * sizeof(c128));
+  SALLOC(c->d_op_of_sub, g.nsub * sizeof(int));
+  SALLOC(c->d_step_subs, c->sch.step_subs.size() * sizeof(int));
+  SALLOC(c->d_all_subs, g.nsub * sizeof(int));
+  SALLOC(c->d_all_ops, c->nops * sizeof(int));
+  SALLOC(c->d_flag, sizeof(int));
+  std::vector<int> iota_s(g.nsub), iota_o(c->nops);
+  for (int i = 0; i < g.nsub; ++i) iota_s[i] = i;
+  for (int i = 0; i < c->nops; ++i) iota_o[i] = i;
+  std::vector<double> kflat((size_t)c->nops * g.sub_nodes);
+  for (int o = 0; o < c->nops; ++o)
+    std::copy(kops[o].begin(), kops[o].end(), kflat.begin() + (size_t)o * g.sub_nodes);
+  hipError_t he = hipSuccess;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (he == hipSuccess) he = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  up(c->d_kappa_sub, kflat.data(), kflat.size() * sizeof(double));
+  up(c->d_kappa, c->kappa.data(), nint * sizeof(double));
+  up(c->d_alpha_sub, al_sub.data(), al_sub.size() * sizeof(c128));
+  up(c->d_alpha_glob, al_glob.data(), al_glob.size() * sizeof(c128));
+  up(c->d_op_of_sub, c->op_of_sub.data(), g.nsub * sizeof(int));
+  up(c->d_step_subs, c->sch.step_subs.data(), c->sch.step_subs.size() * sizeof(int));
+  up(c->d_all_subs, iota_s.data(), g.nsub * sizeof(int));
+  up(c->d_all_ops, iota_o.data(), c->nops * sizeof(int));
+  if (he != hipSuccess) return fail(HDSW_EDEVICE);
+  c->part_blocks = 256;
+  *out = c;
+  return HDSW_OK;
+}
+
+// ------------------------------------------------------------ factor
+template <class T>
+static hdsw_status factor_impl(hdsw_ctx* c) {
+  const Geometry& g = c->g;
+  HCHK(launch_zero(c, c->d_flag, sizeof(int)));
+  HCHK(launch_assemble(c));
+  HCHK(launch_cast_coef<T>(c));
+  {
+    double fl = 8.0 * g.n * (double)g.n * g.n * g.K * c->nops;
+    double by = 2.0 * g.K * (double)g.n * g.n * sizeof(cpx<T>) * c->nops;
+    TimedScope ts(c, KT_FACTOR, fl, by);
+    for (int k = 0; k < g.K; ++k) HCHK(launch_factor_block<T>(c, k));
+  }
+  // interface-to-interface response T = P_I S^{-1} P_I^T of every distinct
+  // operator: block solves with unit sources on the interface dofs
+  const size_t e = sizeof(cpx<T>);
+  size_t per_col = (size_t)g.K * g.n * e;
+  size_t budget = (size_t)1 << 31;
+  int ct = (int)std::min<size_t>(g.NI, std::max<size_t>(1, budget / per_col));
+  void* tmp = nullptr;
+  ACHK(dev_alloc(c, &tmp, per_col * ct));
+  void* saved = c->d_panel;
+  c->d_panel = tmp;
+  for (int op = 0; op < c->nops; ++op) {
+    for (int col0 = 0; col0 < g.NI; col0 += ct) {
+      int nc = std::min(ct, g.NI - col0);
+      hipError_t r1 = launch_fill_panel<T>(c, 2, 1, c->d_all_ops + op, nc, nullptr, col0);
+      hipError_t r2 = r1 == hipSuccess ? launch_block_solve<T>(c, 1, c->d_all_ops + op, nc) : r1;
+      hipError_t r3 = r2 == hipSuccess
+                          ? launch_extract_iface<T>(c, 1, nc,
+                                                    (cpx<T>*)c->d_T + (size_t)op * g.NI * g.NI +
+                                                        (size_t)col0 * g.NI,
+                                                    0, g.NI)
+                          : r2;
+      if (r3 != hipSuccess) {
+        c->d_panel = saved;
+        dev_free(c, tmp);
+        c->sticky = HDSW_EDEVICE;
+        return HDSW_EDEVICE;
+      }
+    }
+  }
+  HCHK(hipStreamSynchronize(c->stream));
+  c->d_panel = saved;
+  dev_free(c, tmp);
+  int flag = 0;
+  HCHK(hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) return HDSW_EINVAL;  // a singular diagonal block
+  c->factored = true;
+  return HDSW_OK;
+}
+
+hdsw_status factor(hdsw_ctx* c) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (c->factored) return HDSW_OK;
+  return c->opt.precision == HDSW_MIXED ? factor_impl<float>(c) : factor_impl<double>(c);
+}
+
+// ------------------------------------------------------------ workspaces
+static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
+  const Geometry& g = c->g;
+  size_t e = elt(c);
+  if (C > c->Cmax) {
+    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_out, c->d_y,
+                    c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
+    for (void* p : ptrs) dev_free(c, p);
+    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_out = c->d_y = nullptr;
+    c->d_xg = c->d_rg = c->d_bg = nullptr;
+    c->d_part = c->d_norm = nullptr;
+    c->Cmax = 0;
+    void* p;
+    hdsw_status st;
+#define WALLOC(dst, bytes)                \
+  do {                                    \
+    st = dev_alloc(c, &p, (bytes));       \
+    if (st != HDSW_OK) return st;         \
+    dst = decltype(dst)(p);               \
+  } while (0)
+    size_t iface = (size_t)g.nsub * C * g.NI * e;
+    WALLOC(c->d_panel, (size_t)g.nsub * g.K * C * g.n * e);
+    WALLOC(c->d_slots, iface * c->sch.nsweeps);
+    WALLOC(c->d_g, iface);
+    WALLOC(c->d_accg, iface);
+    WALLOC(c->d_out, iface);
+    WALLOC(c->d_y, iface);
+    WALLOC(c->d_xg, (size_t)C * g.glob_nodes * sizeof(c128));
+    WALLOC(c->d_rg, (size_t)C * g.glob_nodes * sizeof(c128));
+    WALLOC(c->d_bg, (size_t)C * g.glob_nodes * sizeof(c128));
+    WALLOC(c->d_part, (size_t)(std::max(c->opt.gmres_m, 0) + 1) * C * c->part_blocks * 2 *
+                          sizeof(double));
+    WALLOC(c->d_norm, (size_t)C * sizeof(double));
+    c->Cmax = C;
+  }
+  if (need_gmres && (c->gm_m != c->opt.gmres_m || !c->d_V || C > c->Cmax)) {
+    dev_free(c, c->d_V);
+    dev_free(c, c->d_Z);
+    dev_free(c, c->d_dots);
+    c->d_V = c->d_Z = c->d_dots = nullptr;
+    int m = c->opt.gmres_m;
+    void* p;
+    hdsw_status st;
+    WALLOC(c->d_V, (size_t)(m + 1) * c->Cmax * g.glob_nodes * sizeof(c128));
+    WALLOC(c->d_Z, (size_t)m * c->Cmax * g.glob_nodes * sizeof(c128));
+    WALLOC(c->d_dots, (size_t)2 * (m + 1) * c->Cmax * sizeof(c128));
+    c->gm_m = m;
+  }
+  return HDSW_OK;
+}
+
+// ------------------------------------------------------------ DDM
+// One application of Algorithm 2.1 to C global-grid right-hand sides r,
+// written (accumulate = 0) or added (accumulate = 1) to out on owned nodes.
+//
+// Every per-step subdomain solve S^{-1}(f_ij [sweep 1] + trace sources) is
+// needed only (a) on the interface layers, to form the outgoing traces, and
+// (b) on owned nodes, summed over sweeps.  (a) is y_ij + T g with
+// y_ij = P_I S^{-1} f_ij (one batched solve before the sweeps) and T the
+// subdomain's interface response; (b) is, by linearity, one solve with the
+// summed right-hand side f_ij + sum_l g_l after the sweeps.
+template <class T>
+static hdsw_status ddm_impl(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
+  const Geometry& g = c->g;
+  const Schedule& s = c->sch;
+  const size_t e = sizeof(cpx<T>);
+  const double solve_fl = 8.0 * (2.0 * g.K - 1) * g.n * (double)g.n * C * g.nsub;
+  const double solve_by = 2.0 * g.K * (double)g.n * g.n * e * c->nops +
+                          4.0 * g.K * (double)g.n * C * e * g.nsub;
+  HCHK(launch_fill_panel<T>(c, 0, g.nsub, c->d_all_subs, C, r, 0));
+  {
+    TimedScope ts(c, KT_SOLVE, solve_fl, solve_by);
+    HCHK(launch_block_solve<T>(c, g.nsub, c->d_op_of_sub, C));
+  }
+  HCHK(launch_extract_iface<T>(c, g.nsub, C, c->d_y, (long long)C * g.NI, g.NI));
+  size_t iface = (size_t)g.nsub * C * g.NI * e;
+  HCHK(launch_zero(c, c->d_slots, iface * s.nsweeps));
+  HCHK(launch_zero(c, c->d_accg, iface));
+  for (int L = 0; L < s.nsweeps; ++L) {
+    for (int st = 0; st < s.nsteps; ++st) {
+      int off = s.step_off[L * s.nsteps + st], cnt = s.step_cnt[L * s.nsteps + st];
+      if (cnt == 0) continue;
+      HCHK(launch_trace_source<T>(c, L, off, cnt, C));
+      {
+        double fl = 8.0 * g.NI * (double)g.NI * C * cnt;
+        double by = (double)g.NI * g.NI * e * std::min(cnt, c->nops) + 3.0 * g.NI * C * e * cnt;
+        TimedScope ts(c, KT_GEMM, fl, by);
+        HCHK(launch_iface_gemm<T>(c, off, cnt, C, L == 0 ? 1 : 0));
+      }
+      HCHK(launch_route<T>(c, L, off, cnt, C));
+    }
+  }
+  HCHK(launch_fill_panel<T>(c, 1, g.nsub, c->d_all_subs, C, r, 0));
+  {
+    TimedScope ts(c, KT_SOLVE, solve_fl, solve_by);
+    HCHK(launch_block_solve<T>(c, g.nsub, c->d_op_of_sub, C));
+  }
+  HCHK(launch_write_owned<T>(c, C, out, accumulate));
+  return HDSW_OK;
+}
+
+static hdsw_status ddm(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
+  return c->opt.precision == HDSW_MIXED ? ddm_impl<float>(c, r, out, C, accumulate)
+                                        : ddm_impl<double>(c, r, out, C, accumulate);
+}
+
+hdsw_status ddm_dispatch(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
+  return ddm(c, r, out, C, accumulate);
+}
+
+static size_t max_cols(hdsw_ctx* c) {
+  // columns per pass under the budget (0 budget: all requested columns)
+  if (!c->opt.hbm_budget) return 1u << 30;
+  const Geometry& g = c->g;
+  size_t e = elt(c);
+  size_t per_col = (size_t)g.nsub * g.K * g.n * e +
+                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + 4) +
+                   3 * (size_t)g.glob_nodes * sizeof(c128);
+  if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
+  size_t used = c->alloc_bytes;
+  // workspaces currently held can be reused
+  if (c->Cmax > 0) used -= std::min(used, (size_t)c->Cmax * per_col);
+  if (used >= c->opt.hbm_budget) return 0;
+  return (c->opt.hbm_budget - used) / per_col;
+}
+
+hdsw_status apply_precond(hdsw_ctx* c, const c128* r, c128* z, int nrhs) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (!c->factored) return HDSW_ENOTFACTORED;
+  if (!r || !z || nrhs < 1) return HDSW_EINVAL;
+  int chunk = (int)std::min<size_t>(nrhs, max_cols(c));
+  if (chunk < 1) return HDSW_ENOMEM;
+  ACHK(ensure_ws(c, chunk, false));
+  for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+    int C = std::min(chunk, nrhs - c0);
+    ACHK(ddm(c, r + (size_t)c0 * c->g.glob_nodes, z + (size_t)c0 * c->g.glob_nodes, C, 0));
+  }
+  HCHK(hipStreamSynchronize(c->stream));
+  return HDSW_OK;
+}
+
+hdsw_status residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, int nrhs,
+                     double* rn) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (!b || !x || !r || nrhs < 1) return HDSW_EINVAL;
+  ACHK(ensure_ws(c, std::min(nrhs, std::max(c->Cmax, 1)), false));
+  for (int c0 = 0; c0 < nrhs; c0 += c->Cmax) {
+    int C = std::min(c->Cmax, nrhs - c0);
+    size_t o = (size_t)c0 * c->g.glob_nodes;
+    HCHK(launch_residual(c, b + o, x + o, r + o, C));
+    if (rn) {
+      HCHK(launch_norms(c, r + o, C, c->d_norm));
+      HCHK(hipMemcpyAsync(rn + c0, c->d_norm, C * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    }
+  }
+  HCHK(hipStreamSynchronize(c->stream));
+  return HDSW_OK;
+}
+
+// ------------------------------------------------------------ Krylov
+// FP64 iterative refinement, x_{j+1} = x_j + M^{-1}(b - S x_j), for C
+// columns held in the context's global buffers.
+static hdsw_status refine_cols(hdsw_ctx* c, int C, std::vector<int>& iters,
+                               std::vector<double>& rel, const std::vector<double>& bn) {
+  const Geometry& g = c->g;
+  HCHK(launch_zero(c, c->d_xg, (size_t)C * g.glob_nodes * sizeof(c128)));
+  std::vector<double> rn(C);
+  iters.assign(C, -1);
+  rel.assign(C, 0.0);
+  for (int it = 0; it <= c->opt.max_iter; ++it) {
+    {
+      TimedScope ts(c, KT_RESID, 22.0 * g.glob_nodes * C, 48.0 * g.glob_nodes * C);
+      HCHK(launch_residual(c, c->d_bg, c->d_xg, c->d_rg, C));
+    }
+    HCHK(launch_norms(c, c->d_rg, C, c->d_norm));
+    HCHK(hipMemcpyAsync(rn.data(), c->d_norm, C * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+    HCHK(hipStreamSynchronize(c->stream));
+    bool all = true;
+    for (int j = 0; j < C; ++j) {
+      rel[j] = bn[j] > 0 ? rn[j] / bn[j] : 0.0;
+      if (iters[j] < 0 && rel[j] <= c->opt.tol) iters[j] = it;
+      if (iters[j] < 0) all = false;
+    }
+    if (all || it == c->opt.max_iter) break;
+    ACHK(ddm(c, c->d_rg, c->d_xg, C, 1));
+  }
+  return HDSW_OK;
+}
+
+hdsw_status gmres_cols(hdsw_ctx* c, int C, std::vector<int>& iters, std::vector<double>& rel,
+                       const std::vector<double>& bn);
+
+hdsw_status solve(hdsw_ctx* c, const c128* f, c128* x, int nrhs, hdsw_solve_info* info) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (!c->factored) return HDSW_ENOTFACTORED;
+  if (!f || !x || nrhs < 1) return HDSW_EINVAL;
+  int chunk = (int)std::min<size_t>(nrhs, max_cols(c));
+  if (chunk < 1) return HDSW_ENOMEM;
+  bool gm = c->opt.gmres_m > 0;
+  ACHK(ensure_ws(c, chunk, gm));
+  const Geometry& g = c->g;
+  bool conv = true;
+  for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+    int C = std::min(chunk, nrhs - c0);
+    HCHK(launch_rhs_from_f(c, f + (size_t)c0 * g.int_nodes, c->d_bg, C));
+    HCHK(launch_norms(c, c->d_bg, C, c->d_norm));
+    std::vector<double> bn(C);
+    HCHK(hipMemcpyAsync(bn.data(), c->d_norm, C * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+    HCHK(hipStreamSynchronize(c->stream));
+    std::vector<int> iters;
+    std::vector<double> rel;
+    if (gm) ACHK(gmres_cols(c, C, iters, rel, bn));
+    else ACHK(refine_cols(c, C, iters, rel, bn));
+    HCHK(launch_extract_interior(c, c->d_xg, x + (size_t)c0 * g.int_nodes, C));
+    for (int j = 0; j < C; ++j) {
+      if (iters[j] < 0) conv = false;
+      if (info) {
+        info[c0 + j].iters = iters[j] < 0 ? c->opt.max_iter : iters[j];
+        info[c0 + j].rel_residual = rel[j];
+      }
+    }
+  }
+  HCHK(hipStreamSynchronize(c->stream));
+  return conv ? HDSW_OK : HDSW_ENOCONV;
+}
+
+hdsw_status timing_get(hdsw_ctx* c, int which, double* ms, long long* n, double* fl,
+                       double* by) {
+  if (which < 0 || which > 3) return HDSW_EINVAL;
+  resolve_timing(c);
+  if (ms) *ms = c->tm.ms[which];
+  if (n) *n = c->tm.launches[which];
+  if (fl) *fl = c->tm.flops[which];
+  if (by) *by = c->tm.bytes[which];
+  c->tm.ms[which] = 0;
+  c->tm.launches[which] = 0;
+  c->tm.flops[which] = 0;
+  c->tm.bytes[which] = 0;
+  return HDSW_OK;
+}
+
+void destroy(hdsw_ctx* c) {
+  if (!c) return;
+  resolve_timing(c);
+  pending().erase(c);
+  for (auto& b : c->bufs) (void)hipFree(b.p);
+  delete c;
+}
+
+}  // namespace hdsw

@@ -1,0 +1,245 @@
+// Internal declarations of the hdsw library: complex arithmetic, geometry,
+// schedule, context and kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdsw.h"
+
+namespace hdsw {
+
+// ---------------------------------------------------------------- complex
+template <class T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+template <class T>
+__host__ __device__ inline cpx<T> mk(T r, T i) {
+  cpx<T> z;
+  z.re = r;
+  z.im = i;
+  return z;
+}
+template <class T>
+__host__ __device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) {
+  return mk<T>(a.re + b.re, a.im + b.im);
+}
+template <class T>
+__host__ __device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) {
+  return mk<T>(a.re - b.re, a.im - b.im);
+}
+template <class T>
+__host__ __device__ inline cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return mk<T>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class T>
+__host__ __device__ inline cpx<T> operator-(cpx<T> a) {
+  return mk<T>(-a.re, -a.im);
+}
+// acc += a * b
+template <class T>
+__host__ __device__ inline void cfma(cpx<T>& acc, cpx<T> a, cpx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+template <class T>
+__host__ __device__ inline cpx<T> cinv(cpx<T> a) {
+  // 1 / a with scaling against overflow (Smith's method)
+  if (fabs(a.re) >= fabs(a.im)) {
+    if (a.re == T(0)) return mk<T>(T(0), T(0));
+    T r = a.im / a.re, d = a.re + a.im * r;
+    return mk<T>(T(1) / d, -r / d);
+  }
+  T r = a.re / a.im, d = a.im + a.re * r;
+  return mk<T>(r / d, T(-1) / d);
+}
+template <class T, class U>
+__host__ __device__ inline cpx<T> ccast(cpx<U> a) {
+  return mk<T>(T(a.re), T(a.im));
+}
+
+using c64 = cpx<float>;
+using c128 = cpx<double>;
+
+// ---------------------------------------------------------------- geometry
+// Per-axis sizes of the problem and partition.  Axis 0 = x (fastest).
+struct Geometry {
+  int dim = 2;
+  int N[3] = {1, 1, 1};    // interior nodes per axis
+  int P[3] = {1, 1, 1};    // subdomains per axis
+  int na[3] = {1, 1, 1};   // interior nodes per subdomain per axis
+  int ne[3] = {1, 1, 1};   // extended nodes per subdomain per axis (na + 2W)
+  int M[3] = {1, 1, 1};    // global nodes per axis (N + 2W)
+  int W = 1;
+  double h = 1.0;
+  double s0 = 0.0;         // sigma0
+  int nsub = 1;
+  // 2D block structure: x-lines (n = ne[0]) indexed by y (K = ne[1]).
+  // 3D block structure: xy-planes (n = ne[0] ne[1]) indexed by z (K = ne[2]).
+  int n = 1, K = 1;
+  long long sub_nodes = 1;     // nodes of one extended subdomain
+  long long glob_nodes = 1;    // nodes of the global grid
+  long long int_nodes = 1;     // interior nodes
+  // interface dofs: per side 2 layers x tangential extent
+  int nsides = 4;
+  int side_len[6] = {0};       // tangential extent of each side
+  int side_off[6] = {0};       // offset of each side in the interface vector
+  int NI = 0;                  // interface dofs per subdomain
+
+  void sub_coords(int s, int c[3]) const {
+    c[0] = s % P[0];
+    c[1] = (s / P[0]) % P[1];
+    c[2] = s / (P[0] * P[1]);
+  }
+  int sub_id(const int c[3]) const { return c[0] + P[0] * (c[1] + P[1] * c[2]); }
+};
+
+// Device-side view of the geometry (plain struct passed by value).
+struct GeoDev {
+  int dim, W, n, K, NI, nsub;
+  int N[3], P[3], na[3], ne[3], M[3];
+  int side_len[6], side_off[6];
+};
+
+// Sweep schedule (eq. Sorder2D / Sorder3D, eq. step_subd / step_subd3) and
+// trace routing (Rules 2.4/2.5, 4.1/4.2 over the extended sweep list).
+struct Schedule {
+  int nsweeps = 0;                       // rounds * 2^dim
+  std::vector<std::array<int, 3>> dir;   // direction of each sweep
+  int nsteps = 0;                        // steps per sweep
+  // for every (sweep, step): offset into step_subs and count
+  std::vector<int> step_off, step_cnt;
+  std::vector<int> step_subs;            // concatenated subdomain ids
+  // lprime[L * 6 + face] = sweep that uses a trace generated in sweep L
+  // across face (0:-x,1:+x,2:-y,3:+y,4:-z,5:+z); -1 = dropped
+  std::vector<int> lprime;
+};
+
+// ---------------------------------------------------------------- buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Timing {
+  bool on = false;
+  double ms[4] = {0, 0, 0, 0};
+  long long launches[4] = {0, 0, 0, 0};
+  double flops[4] = {0, 0, 0, 0};
+  double bytes[4] = {0, 0, 0, 0};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+}  // namespace hdsw
+
+struct hdsw_ctx {
+  hdsw::Geometry g;
+  hdsw::GeoDev gd;
+  hdsw::Schedule sch;
+  hdsw_options opt;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<double> kappa;     // interior wavenumber (host copy)
+  int nops = 0;
+  std::vector<int> op_of_sub;    // subdomain -> distinct operator
+  std::vector<int> rep_of_op;    // distinct operator -> representative subdomain
+  bool factored = false;
+  hdsw_status sticky = HDSW_OK;
+  size_t alloc_bytes = 0;
+  size_t factor_bytes = 0;
+  std::vector<hdsw::DevBuf> bufs;   // every allocation, freed in destroy
+
+  // device arrays (precision independent)
+  int* d_op_of_sub = nullptr;
+  int* d_step_subs = nullptr;
+  int* d_all_subs = nullptr;        // 0..nsub-1
+  int* d_all_ops = nullptr;         // 0..nops-1
+  double* d_kappa = nullptr;        // interior kappa
+  hdsw::c128* d_coef = nullptr;     // per op: operator coefficients (double)
+  size_t coef_stride = 0;           // complex entries per op
+  hdsw::c128* d_alpha_sub = nullptr;   // local alpha: node/half per axis
+  hdsw::c128* d_alpha_glob = nullptr;  // global alpha: node/half per axis
+  int alpha_sub_off[6] = {0};          // node_x, half_x, node_y, half_y, node_z, half_z
+  int alpha_glob_off[6] = {0};
+  double* d_kappa_sub = nullptr;    // per op: kappa on the extended grid
+  int* d_flag = nullptr;            // device error flag (singular pivot)
+
+  // precision-dependent factors: element type cpx<float> or cpx<double>
+  void* d_X = nullptr;              // [nops][K][n][n] column-major blocks
+  void* d_T = nullptr;              // [nops][NI][NI] column-major (2D)
+  void* d_coefT = nullptr;          // coefficients in working precision
+
+  // workspaces sized for Cmax columns
+  int Cmax = 0;
+  void* d_panel = nullptr;          // [nsub][K][C][n]
+  void* d_slots = nullptr;          // [nsweeps][nsub][C][NI]
+  void* d_g = nullptr;              // [nsub][C][NI] trace sources of a step
+  void* d_accg = nullptr;           // [nsub][C][NI] accumulated sources
+  void* d_out = nullptr;            // [nsub][C][NI] interface outputs
+  void* d_y = nullptr;              // [nsub][C][NI] source-driven outputs
+  hdsw::c128* d_xg = nullptr;       // [C][glob] iterate (FP64)
+  hdsw::c128* d_rg = nullptr;       // [C][glob] residual (FP64)
+  hdsw::c128* d_bg = nullptr;       // [C][glob] right-hand side (FP64)
+  double* d_part = nullptr;         // partial norms
+  double* d_norm = nullptr;         // [C] norms
+  int part_blocks = 0;
+  // GMRES workspace
+  int gm_m = 0;
+  hdsw::c128* d_V = nullptr;        // [m+1][C][glob]
+  hdsw::c128* d_Z = nullptr;        // [m][C][glob]
+  hdsw::c128* d_dots = nullptr;     // [m+1][C]
+  hdsw::Timing tm;
+};
+
+namespace hdsw {
+
+// kernel classes for timing
+enum { KT_SOLVE = 0, KT_GEMM = 1, KT_FACTOR = 2, KT_RESID = 3 };
+
+// ----- launchers (kernels.hip) ------------------------------------------
+hipError_t launch_assemble(hdsw_ctx* c);
+template <class T>
+hipError_t launch_cast_coef(hdsw_ctx* c);
+template <class T>
+hipError_t launch_factor_block(hdsw_ctx* c, int k);
+template <class T>
+hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids,
+                             int C, const c128* rglob, int unit_col0);
+template <class T>
+hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops_of_batch,
+                              int C);
+template <class T>
+hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
+                                long long dst_stride_batch, int dst_ld);
+template <class T>
+hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate);
+template <class T>
+hipError_t launch_trace_source(hdsw_ctx* c, int L, int off, int cnt, int C);
+template <class T>
+hipError_t launch_iface_gemm(hdsw_ctx* c, int off, int cnt, int C, int add_y);
+template <class T>
+hipError_t launch_route(hdsw_ctx* c, int L, int off, int cnt, int C);
+hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C);
+hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r,
+                           int C);
+hipError_t launch_norms(hdsw_ctx* c, const c128* v, int C, double* d_out);
+hipError_t launch_extract_interior(hdsw_ctx* c, const c128* glob, c128* out,
+                                   int C);
+hipError_t launch_zero(hdsw_ctx* c, void* p, size_t bytes);
+// GMRES helpers (FP64)
+hipError_t launch_dots(hdsw_ctx* c, const c128* V, int nv, const c128* w, int C,
+                       c128* d_out);
+hipError_t launch_axpy_multi(hdsw_ctx* c, c128* w, const c128* V, int nv,
+                             const c128* coef, int C, double sign);
+hipError_t launch_scale(hdsw_ctx* c, c128* dst, const c128* src, const double* inv,
+                        int C);
+
+}  // namespace hdsw

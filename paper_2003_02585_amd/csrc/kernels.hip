@@ -1,0 +1,935 @@
+// HIP kernels of the hdsw library (gfx950).  Every kernel bounds-checks its
+// indices against the sizes it is given; launchers check shapes on the host.
+//
+// Data layout in HBM (x fastest everywhere):
+//   operator coefficients, per distinct subdomain operator (2D):
+//     ax[K][n+1]  x-face coefficients a^x at the half-points between local
+//                 x-nodes q-1 and q (q = 0..n, ghost faces included)
+//     ay[K+1][n]  y-face coefficients a^y
+//     dg[K][n]    diagonal h^2 k^2 J - (sum of the four face coefficients)
+//   factors X[op][k][n][n]: X_k = D_k^{-1}, column-major (entry (r, j) at
+//     j*n + r), so a thread per row reads consecutive addresses.
+//   panels [batch][k][c][n]: right-hand sides / solutions of a batch of
+//     subdomain solves, block k (grid line), column c, in-block index.
+//   interface vectors [sub][c][NI]: the two layers next to each face, side
+//     order -x, +x, -y, +y, layer 0 = the subdomain's own boundary layer,
+//     layer 1 = the adjacent layer inside its own PML.
+//   trace slots [sweep][sub][c][NI]: received pairs, in the receiver's
+//     layer-0 / layer-1 convention.
+//   global vectors [c][M_y][M_x] complex128.
+#include "hdsw_internal.hpp"
+
+namespace hdsw {
+
+// ------------------------------------------------------------ helpers
+__device__ inline int iface_dof_x(const GeoDev& g, int p, int k) {
+  // x-side interface dof of local node (p, k) in 2D, -1 if none
+  int W = g.W, na = g.na[0];
+  int s = -1, L = 0;
+  if (p == W) { s = 0; L = 0; }
+  else if (p == W - 1) { s = 0; L = 1; }
+  else if (p == W + na - 1) { s = 1; L = 0; }
+  else if (p == W + na) { s = 1; L = 1; }
+  if (s < 0) return -1;
+  return g.side_off[s] + L * g.side_len[s] + k;
+}
+__device__ inline int iface_dof_y(const GeoDev& g, int p, int k) {
+  int W = g.W, na = g.na[1];
+  int s = -1, L = 0;
+  if (k == W) { s = 2; L = 0; }
+  else if (k == W - 1) { s = 2; L = 1; }
+  else if (k == W + na - 1) { s = 3; L = 0; }
+  else if (k == W + na) { s = 3; L = 1; }
+  if (s < 0) return -1;
+  return g.side_off[s] + L * g.side_len[s] + p;
+}
+// local node (p, k) of interface dof i (2D)
+__device__ inline void dof_node2d(const GeoDev& g, int i, int& p, int& k) {
+  int s = 0;
+  while (s < 3 && i >= g.side_off[s + 1]) ++s;
+  int r = i - g.side_off[s];
+  int L = r / g.side_len[s];
+  int t = r - L * g.side_len[s];
+  int axis = s >> 1;
+  int na = g.na[axis];
+  int layer = (s & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
+  if (axis == 0) { p = layer; k = t; }
+  else { p = t; k = layer; }
+}
+__device__ inline bool owned_axis(const GeoDev& g, int a, int bc, int loc) {
+  return (loc >= g.W || bc == 0) && (loc < g.W + g.na[a] || bc == g.P[a] - 1);
+}
+
+// ------------------------------------------------------------ assembly
+// Operator coefficients of every distinct subdomain operator (2D), from the
+// local alpha profiles (identical for all subdomains: they depend only on
+// the offset from the subdomain's own box) and the extended wavenumber.
+__global__ void k_assemble2d(c128* coef, size_t stride, const c128* al, int o_nx,
+                             int o_hx, int o_ny, int o_hy, const double* kap,
+                             GeoDev g, double h2, int nops) {
+  int op = blockIdx.y;
+  if (op >= nops) return;
+  int n = g.n, K = g.K;
+  c128* ax = coef + (size_t)op * stride;
+  c128* ay = ax + (size_t)K * (n + 1);
+  c128* dg = ay + (size_t)(K + 1) * n;
+  const double* kp = kap + (size_t)op * n * K;
+  int tot1 = K * (n + 1), tot2 = (K + 1) * n;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot1 + tot2;
+       idx += gridDim.x * blockDim.x) {
+    if (idx < tot1) {
+      int k = idx / (n + 1), q = idx - k * (n + 1);
+      ax[idx] = al[o_ny + k] * cinv(al[o_hx + q]);
+    } else {
+      int j = idx - tot1;
+      int q = j / n, p = j - q * n;
+      ay[j] = al[o_nx + p] * cinv(al[o_hy + q]);
+    }
+  }
+  __syncthreads();
+  // diagonal needs the faces: recompute them locally (no cross-block sync)
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * K;
+       idx += gridDim.x * blockDim.x) {
+    int k = idx / n, p = idx - k * n;
+    c128 axl = al[o_ny + k] * cinv(al[o_hx + p]);
+    c128 axr = al[o_ny + k] * cinv(al[o_hx + p + 1]);
+    c128 ayl = al[o_nx + p] * cinv(al[o_hy + k]);
+    c128 ayr = al[o_nx + p] * cinv(al[o_hy + k + 1]);
+    double kk = kp[idx];
+    c128 J = al[o_nx + p] * al[o_ny + k];
+    c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
+    dg[idx] = d - axl - axr - ayl - ayr;
+  }
+}
+
+hipError_t launch_assemble(hdsw_ctx* c) {
+  const Geometry& g = c->g;
+  int tot = g.K * (g.n + 1) + (g.K + 1) * g.n;
+  dim3 grid((tot + 255) / 256, c->nops);
+  hipLaunchKernelGGL(k_assemble2d, grid, dim3(256), 0, c->stream, c->d_coef,
+                     c->coef_stride, c->d_alpha_sub, c->alpha_sub_off[0],
+                     c->alpha_sub_off[1], c->alpha_sub_off[2], c->alpha_sub_off[3],
+                     c->d_kappa_sub, c->gd, g.h * g.h, c->nops);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void k_cast_coef(cpx<T>* dst, const c128* src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = ccast<T>(src[i]);
+}
+template <class T>
+hipError_t launch_cast_coef(hdsw_ctx* c) {
+  size_t n = c->coef_stride * c->nops;
+  int blocks = (int)std::min<size_t>((n + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_cast_coef<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (cpx<T>*)c->d_coefT, c->d_coef, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ factor
+// One block row of the block-tridiagonal LU of every distinct operator:
+//   D_k = A_k - B_k X_{k-1} B_k  (B_k = diag of the y-faces between lines
+//   k-1 and k), then X_k = D_k^{-1} by in-place Gauss-Jordan elimination
+//   with partial pivoting (largest |re|+|im| in the pivot column, lowest
+//   row index on ties).  The matrix is handled in its transposed row-major
+//   form, so the inverse lands column-major.  One workgroup per operator.
+template <class T>
+__global__ __launch_bounds__(1024) void k_factor_block(cpx<T>* X, size_t xstride,
+                                                       const cpx<T>* coefT,
+                                                       size_t cstride, GeoDev g,
+                                                       int k, int* flag, int nops) {
+  extern __shared__ unsigned char smem_raw[];
+  int op = blockIdx.x;
+  if (op >= nops) return;
+  const int n = g.n, K = g.K;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  cpx<T>* rowv = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* colv = rowv + n;
+  int* perm = reinterpret_cast<int*>(colv + n);
+  T* redv = reinterpret_cast<T*>(perm + ((n + 3) & ~3));
+  int* redi = reinterpret_cast<int*>(redv + bs);
+
+  cpx<T>* M = X + (size_t)op * xstride + (size_t)k * n * n;
+  const cpx<T>* prev = k > 0 ? M - (size_t)n * n : nullptr;
+  const cpx<T>* ax = coefT + (size_t)op * cstride + (size_t)k * (n + 1);
+  const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1) + (size_t)k * n;
+  const cpx<T>* dg = coefT + (size_t)op * cstride + (size_t)K * (n + 1) +
+                     (size_t)(K + 1) * n + (size_t)k * n;
+  // build D_k (symmetric: its transpose has the same formula)
+  for (int idx = tid; idx < n * n; idx += bs) {
+    int i = idx / n, j = idx - i * n;
+    cpx<T> v = mk<T>(T(0), T(0));
+    if (i == j) v = dg[i];
+    else if (j == i + 1) v = ax[j];
+    else if (i == j + 1) v = ax[i];
+    if (prev) v = v - ay[i] * ay[j] * prev[idx];
+    M[idx] = v;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    // pivot search in column j, rows j..n-1
+    T best = T(-1);
+    int bi = n;
+    for (int i = j + tid; i < n; i += bs) {
+      cpx<T> a = M[(size_t)i * n + j];
+      T m = fabs(a.re) + fabs(a.im);
+      if (m > best) { best = m; bi = i; }
+    }
+    redv[tid] = best;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int s = bs / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        T ob = redv[tid + s];
+        int oi = redi[tid + s];
+        if (ob > redv[tid] || (ob == redv[tid] && oi < redi[tid])) {
+          redv[tid] = ob;
+          redi[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    int p = redi[0];
+    if (p >= n) p = j;
+    if (tid == 0) perm[j] = p;
+    if (p != j) {
+      for (int jj = tid; jj < n; jj += bs) {
+        cpx<T> a = M[(size_t)j * n + jj];
+        M[(size_t)j * n + jj] = M[(size_t)p * n + jj];
+        M[(size_t)p * n + jj] = a;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    cpx<T> piv = M[(size_t)j * n + j];
+    if (piv.re == T(0) && piv.im == T(0)) {
+      if (tid == 0) atomicExch(flag, 1);
+    }
+    cpx<T> inv = cinv(piv);
+    for (int jj = tid; jj < n; jj += bs) rowv[jj] = (jj == j) ? inv : M[(size_t)j * n + jj] * inv;
+    for (int i = tid; i < n; i += bs) colv[i] = M[(size_t)i * n + j];
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += bs) {
+      int i = idx / n, jj = idx - i * n;
+      if (i == j) {
+        M[idx] = rowv[jj];
+      } else if (jj == j) {
+        M[idx] = -(colv[i] * inv);
+      } else {
+        cpx<T> m = M[idx];
+        cpx<T> cv = colv[i], rv = rowv[jj];
+        m.re = fma(-cv.re, rv.re, m.re);
+        m.re = fma(cv.im, rv.im, m.re);
+        m.im = fma(-cv.re, rv.im, m.im);
+        m.im = fma(-cv.im, rv.re, m.im);
+        M[idx] = m;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int j = n - 1; j >= 0; --j) {
+    int p = perm[j];
+    if (p != j) {
+      for (int i = tid; i < n; i += bs) {
+        cpx<T> a = M[(size_t)i * n + j];
+        M[(size_t)i * n + j] = M[(size_t)i * n + p];
+        M[(size_t)i * n + p] = a;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+template <class T>
+hipError_t launch_factor_block(hdsw_ctx* c, int k) {
+  const Geometry& g = c->g;
+  int bs = 1024;
+  size_t lds = 2 * g.n * sizeof(cpx<T>) + ((g.n + 3) & ~3) * sizeof(int) +
+               bs * (sizeof(T) + sizeof(int));
+  size_t xstride = (size_t)g.K * g.n * g.n;
+  hipLaunchKernelGGL(k_factor_block<T>, dim3(c->nops), dim3(bs), lds, c->stream,
+                     (cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
+                     c->coef_stride, c->gd, k, c->d_flag, c->nops);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ panels
+// mode 0: owned part of a global FP64 vector, cast to the working precision
+// mode 1: mode 0 plus the accumulated interface sources (scatter P_I^T)
+// mode 2: unit vectors of interface dofs unit_col0 .. unit_col0 + C - 1
+// batch entry b is subdomain ids[b] (modes 0, 1) or operator ids[b] (mode 2)
+template <class T>
+__global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch,
+                             int C, const c128* rg, const cpx<T>* accg, GeoDev g,
+                             long long glob, int col0) {
+  const int n = g.n, K = g.K;
+  long long per = (long long)K * C * n;
+  long long tot = per * nbatch;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int b = (int)(idx / per);
+    long long r = idx - b * per;
+    int k = (int)(r / ((long long)C * n));
+    int rem = (int)(r - (long long)k * C * n);
+    int col = rem / n, p = rem - col * n;
+    cpx<T> v = mk<T>(T(0), T(0));
+    if (mode == 2) {
+      int d = col0 + col;
+      if (iface_dof_x(g, p, k) == d || iface_dof_y(g, p, k) == d) v.re = T(1);
+    } else {
+      int s = ids[b];
+      int bx = s % g.P[0], by = s / g.P[0];
+      if (owned_axis(g, 0, bx, p) && owned_axis(g, 1, by, k)) {
+        long long G = (long long)(by * g.na[1] + k) * g.M[0] + (bx * g.na[0] + p);
+        v = ccast<T>(rg[(long long)col * glob + G]);
+      }
+      if (mode == 1) {
+        const cpx<T>* a = accg + ((long long)s * C + col) * g.NI;
+        int dx = iface_dof_x(g, p, k), dy = iface_dof_y(g, p, k);
+        if (dx >= 0) v = v + a[dx];
+        if (dy >= 0) v = v + a[dy];
+      }
+    }
+    panel[idx] = v;
+  }
+}
+
+template <class T>
+hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids,
+                             int C, const c128* rglob, int unit_col0) {
+  long long tot = (long long)c->g.K * C * c->g.n * nbatch;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_fill_panel<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (cpx<T>*)c->d_panel, mode, d_ids, nbatch, C, rglob,
+                     (const cpx<T>*)c->d_accg, c->gd, c->g.glob_nodes, unit_col0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ block solve
+// Batched multi-RHS block-tridiagonal solve with the stored inverses:
+//   forward   w_0 = X_0 f_0,  w_k = X_k (f_k - B_k w_{k-1})
+//   backward  x_{K-1} = w_{K-1},  x_k = w_k - X_k (B_{k+1} x_{k+1})
+// One workgroup per (batch entry, tile of CT columns); each thread owns up
+// to RPT rows and keeps CT complex accumulators per row.  The vector being
+// multiplied sits in LDS and is read as a broadcast; X_k is streamed with
+// consecutive rows in consecutive lanes.
+template <class T, int CT, int RPT>
+__global__ __launch_bounds__(256) void k_block_solve(const cpx<T>* __restrict__ X,
+                                                     size_t xstride,
+                                                     const cpx<T>* __restrict__ coefT,
+                                                     size_t cstride,
+                                                     cpx<T>* __restrict__ panel,
+                                                     const int* __restrict__ ops, GeoDev g,
+                                                     int C, int nbatch) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n = g.n, K = g.K;
+  const int b = blockIdx.y;
+  if (b >= nbatch) return;
+  const int c0 = blockIdx.x * CT;
+  const int nc = min(CT, C - c0);
+  const int op = ops[b];
+  const int tid = threadIdx.x;
+  cpx<T>* v = reinterpret_cast<cpx<T>*>(smem_raw);    // [CT][n]
+  cpx<T>* w = v + CT * n;                              // [CT][n]
+  const cpx<T>* Xo = X + (size_t)op * xstride;
+  const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
+  cpx<T>* pb = panel + (size_t)b * K * C * n;
+
+  cpx<T> acc[RPT][CT];
+  for (int k = 0; k < K; ++k) {
+    for (int idx = tid; idx < CT * n; idx += 256) {
+      int cc = idx / n, r = idx - cc * n;
+      cpx<T> val = mk<T>(T(0), T(0));
+      if (cc < nc) val = pb[((size_t)k * C + c0 + cc) * n + r];
+      if (k > 0) val = val - ay[(size_t)k * n + r] * w[cc * n + r];
+      v[idx] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) acc[q][cc] = mk<T>(T(0), T(0));
+    const cpx<T>* Xk = Xo + (size_t)k * n * n;
+    for (int j = 0; j < n; ++j) {
+      cpx<T> vj[CT];
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) vj[cc] = v[cc * n + j];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        int r = tid + q * 256;
+        if (r < n) {
+          cpx<T> x = Xk[(size_t)j * n + r];
+#pragma unroll
+          for (int cc = 0; cc < CT; ++cc) cfma(acc[q][cc], x, vj[cc]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      int r = tid + q * 256;
+      if (r < n) {
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) {
+          if (cc < nc) pb[((size_t)k * C + c0 + cc) * n + r] = acc[q][cc];
+          w[cc * n + r] = acc[q][cc];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = K - 2; k >= 0; --k) {
+    for (int idx = tid; idx < CT * n; idx += 256) {
+      int r = idx % n;
+      v[idx] = ay[(size_t)(k + 1) * n + r] * w[idx];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) acc[q][cc] = mk<T>(T(0), T(0));
+    const cpx<T>* Xk = Xo + (size_t)k * n * n;
+    for (int j = 0; j < n; ++j) {
+      cpx<T> vj[CT];
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) vj[cc] = v[cc * n + j];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        int r = tid + q * 256;
+        if (r < n) {
+          cpx<T> x = Xk[(size_t)j * n + r];
+#pragma unroll
+          for (int cc = 0; cc < CT; ++cc) cfma(acc[q][cc], x, vj[cc]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      int r = tid + q * 256;
+      if (r < n) {
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) {
+          cpx<T> wk = mk<T>(T(0), T(0));
+          if (cc < nc) wk = pb[((size_t)k * C + c0 + cc) * n + r];
+          cpx<T> xk = wk - acc[q][cc];
+          if (cc < nc) pb[((size_t)k * C + c0 + cc) * n + r] = xk;
+          w[cc * n + r] = xk;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class T>
+hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
+  const Geometry& g = c->g;
+  if (g.n > 512) return hipErrorInvalidValue;
+  constexpr int CT = 4;
+  dim3 grid((C + CT - 1) / CT, nbatch);
+  size_t lds = 2 * CT * g.n * sizeof(cpx<T>);
+  size_t xstride = (size_t)g.K * g.n * g.n;
+  if (g.n <= 256)
+    hipLaunchKernelGGL((k_block_solve<T, CT, 1>), grid, dim3(256), lds, c->stream,
+                       (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
+                       c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
+  else
+    hipLaunchKernelGGL((k_block_solve<T, CT, 2>), grid, dim3(256), lds, c->stream,
+                       (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
+                       c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ interface I/O
+// dst[b][col][i] = panel[b][k_i][col][p_i]  (restriction P_I)
+template <class T>
+__global__ void k_extract_iface(const cpx<T>* panel, int nbatch, int C, cpx<T>* dst,
+                                long long dst_sb, int dst_ld, GeoDev g) {
+  long long tot = (long long)nbatch * C * g.NI;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int b = (int)(idx / ((long long)C * g.NI));
+    int r = (int)(idx - (long long)b * C * g.NI);
+    int col = r / g.NI, i = r - col * g.NI;
+    int p, k;
+    dof_node2d(g, i, p, k);
+    dst[b * dst_sb + (long long)col * dst_ld + i] =
+        panel[(((long long)b * g.K + k) * C + col) * g.n + p];
+  }
+}
+template <class T>
+hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
+                                long long dst_sb, int dst_ld) {
+  long long tot = (long long)nbatch * C * c->g.NI;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_extract_iface<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (const cpx<T>*)c->d_panel, nbatch, C, (cpx<T>*)dst, dst_sb,
+                     dst_ld, c->gd);
+  return hipGetLastError();
+}
+
+// glob[col][G] (+)= panel on owned nodes (every global node has exactly one
+// owner, so no two threads touch the same element)
+template <class T>
+__global__ void k_write_owned(const cpx<T>* panel, int C, c128* glob, long long gn,
+                              int accumulate, GeoDev g) {
+  const int n = g.n, K = g.K;
+  long long per = (long long)K * C * n;
+  long long tot = per * g.nsub;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int s = (int)(idx / per);
+    long long r = idx - s * per;
+    int k = (int)(r / ((long long)C * n));
+    int rem = (int)(r - (long long)k * C * n);
+    int col = rem / n, p = rem - col * n;
+    int bx = s % g.P[0], by = s / g.P[0];
+    if (!(owned_axis(g, 0, bx, p) && owned_axis(g, 1, by, k))) continue;
+    long long G = (long long)(by * g.na[1] + k) * g.M[0] + (bx * g.na[0] + p);
+    c128 v = ccast<double>(panel[idx]);
+    c128* dst = glob + (long long)col * gn + G;
+    *dst = accumulate ? (*dst + v) : v;
+  }
+}
+template <class T>
+hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate) {
+  long long tot = (long long)c->g.K * C * c->g.n * c->g.nsub;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_write_owned<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (const cpx<T>*)c->d_panel, C, glob, c->g.glob_nodes, accumulate,
+                     c->gd);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ sweep step
+// Trace -> source (the discrete potential): for a pair received on a face,
+//   g[layer 1] =  c * pair[layer 0],   g[layer 0] = -c * pair[layer 1],
+// c = the receiver's coefficient across that face (= [S_r, chi_r] v).
+// Also accumulates the sources of every sweep for the final owned solve.
+template <class T>
+__global__ void k_trace_source(const cpx<T>* slots, cpx<T>* gbuf, cpx<T>* accg,
+                               const cpx<T>* coefT, size_t cstride, const int* op_of,
+                               const int* subs, int cnt, int L, int C, GeoDev g) {
+  const int NI = g.NI, n = g.n, K = g.K;
+  long long tot = (long long)cnt * C * NI;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int bi = (int)(idx / ((long long)C * NI));
+    int r = (int)(idx - (long long)bi * C * NI);
+    int col = r / NI, i = r - col * NI;
+    int s = subs[bi];
+    int side = 0;
+    while (side < 3 && i >= g.side_off[side + 1]) ++side;
+    int len = g.side_len[side];
+    int rr = i - g.side_off[side];
+    int lay = rr / len, t = rr - lay * len;
+    int partner = g.side_off[side] + (1 - lay) * len + t;
+    const cpx<T>* co = coefT + (size_t)op_of[s] * cstride;
+    cpx<T> cf;
+    if (side < 2) {
+      int q = side == 0 ? g.W : g.W + g.na[0];
+      cf = co[(size_t)t * (n + 1) + q];                   // ax[t][face]
+    } else {
+      int q = side == 2 ? g.W : g.W + g.na[1];
+      cf = co[(size_t)K * (n + 1) + (size_t)q * n + t];   // ay[face][t]
+    }
+    size_t base = ((size_t)s * C + col) * NI;
+    cpx<T> pv = slots[((size_t)L * g.nsub) * C * NI + base + partner];
+    cpx<T> gv = cf * pv;
+    if (lay == 0) gv = -gv;
+    gbuf[base + i] = gv;
+    accg[base + i] = accg[base + i] + gv;
+  }
+}
+template <class T>
+hipError_t launch_trace_source(hdsw_ctx* c, int L, int off, int cnt, int C) {
+  long long tot = (long long)cnt * C * c->g.NI;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_trace_source<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (const cpx<T>*)c->d_slots, (cpx<T>*)c->d_g, (cpx<T>*)c->d_accg,
+                     (const cpx<T>*)c->d_coefT, c->coef_stride, c->d_op_of_sub,
+                     c->d_step_subs + off, cnt, L, C, c->gd);
+  return hipGetLastError();
+}
+
+// out[s][col][:] = T_op(s) * g[s][col][:] (+ y[s][col][:])
+// the subdomain solve of one sweep step restricted to its interface layers
+template <class T, int CT>
+__global__ __launch_bounds__(256) void k_iface_gemm(const cpx<T>* __restrict__ Tm,
+                                                    const cpx<T>* __restrict__ gbuf,
+                                                    const cpx<T>* __restrict__ ybuf,
+                                                    cpx<T>* __restrict__ out,
+                                                    const int* op_of, const int* subs,
+                                                    int C, int NI, int add_y) {
+  __shared__ cpx<T> vs[CT][256];
+  const int s = subs[blockIdx.z];
+  const int c0 = blockIdx.y * CT;
+  const int nc = min(CT, C - c0);
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const cpx<T>* Top = Tm + (size_t)op_of[s] * NI * NI;
+  const cpx<T>* gb = gbuf + ((size_t)s * C + c0) * NI;
+  cpx<T> acc[CT];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc) acc[cc] = mk<T>(T(0), T(0));
+  for (int j0 = 0; j0 < NI; j0 += 256) {
+    int jn = min(256, NI - j0);
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) {
+      int j = threadIdx.x;
+      vs[cc][j] = (cc < nc && j < jn) ? gb[(size_t)cc * NI + j0 + j] : mk<T>(T(0), T(0));
+    }
+    __syncthreads();
+    if (row < NI) {
+      for (int j = 0; j < jn; ++j) {
+        cpx<T> x = Top[(size_t)(j0 + j) * NI + row];
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) cfma(acc[cc], x, vs[cc][j]);
+      }
+    }
+  }
+  if (row < NI) {
+    for (int cc = 0; cc < nc; ++cc) {
+      size_t o = ((size_t)s * C + c0 + cc) * NI + row;
+      cpx<T> v = acc[cc];
+      if (add_y) v = v + ybuf[o];
+      out[o] = v;
+    }
+  }
+}
+template <class T>
+hipError_t launch_iface_gemm(hdsw_ctx* c, int off, int cnt, int C, int add_y) {
+  constexpr int CT = 8;
+  int NI = c->g.NI;
+  dim3 grid((NI + 255) / 256, (C + CT - 1) / CT, cnt);
+  hipLaunchKernelGGL((k_iface_gemm<T, CT>), grid, dim3(256), 0, c->stream,
+                     (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_g,
+                     (const cpx<T>*)c->d_y, (cpx<T>*)c->d_out, c->d_op_of_sub,
+                     c->d_step_subs + off, C, NI, add_y);
+  return hipGetLastError();
+}
+
+// Route the traces of one step to the neighbours' slots (Algorithm 2.1:
+// add the transferred trace to the l'-th local trace of the neighbour).
+// The pair is the limit from the receiver's side: on a face that received a
+// pair in this sweep, the incoming value on the own layer is removed.
+struct LPrime { int v[6]; };
+template <class T>
+__global__ void k_route(cpx<T>* slots, const cpx<T>* out, const int* subs, int cnt,
+                        int L, LPrime lp, int C, GeoDev g) {
+  const int NI = g.NI;
+  const size_t slot_stride = (size_t)g.nsub * C * NI;
+  int maxlen = max(g.side_len[0], g.side_len[2]);
+  long long tot = (long long)cnt * 4 * C * maxlen;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int bi = (int)(idx / (4LL * C * maxlen));
+    int r = (int)(idx - (long long)bi * 4 * C * maxlen);
+    int f = r / (C * maxlen);
+    r -= f * C * maxlen;
+    int col = r / maxlen, t = r - col * maxlen;
+    int len = g.side_len[f];
+    if (t >= len) continue;
+    int lq = lp.v[f];
+    if (lq < 0) continue;
+    int s = subs[bi];
+    int sc[2] = {s % g.P[0], s / g.P[0]};
+    int axis = f >> 1, dir = (f & 1) ? 1 : -1;
+    sc[axis] += dir;
+    if (sc[axis] < 0 || sc[axis] >= g.P[axis]) continue;
+    int recv = sc[0] + g.P[0] * sc[1];
+    int fo = f ^ 1;
+    size_t sb = ((size_t)s * C + col) * NI;
+    size_t rb = (size_t)lq * slot_stride + ((size_t)recv * C + col) * NI;
+    cpx<T> o0 = out[sb + g.side_off[f] + t];
+    cpx<T> o1 = out[sb + g.side_off[f] + len + t];
+    cpx<T> in0 = slots[(size_t)L * slot_stride + sb + g.side_off[f] + t];
+    size_t r0 = rb + g.side_off[fo] + t, r1 = rb + g.side_off[fo] + len + t;
+    slots[r0] = slots[r0] + o1;
+    slots[r1] = slots[r1] + (o0 - in0);
+  }
+}
+template <class T>
+hipError_t launch_route(hdsw_ctx* c, int L, int off, int cnt, int C) {
+  LPrime lp;
+  for (int f = 0; f < 6; ++f) lp.v[f] = c->sch.lprime[L * 6 + f];
+  int maxlen = std::max(c->g.side_len[0], c->g.side_len[2]);
+  long long tot = (long long)cnt * 4 * C * maxlen;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_route<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_out,
+                     c->d_step_subs + off, cnt, L, lp, C, c->gd);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ FP64 global
+// b = h^2 J f on the global grid (J = 1 inside B, f = 0 in the layer)
+__global__ void k_rhs_from_f(const c128* f, c128* b, int C, GeoDev g, double h2,
+                             long long gn) {
+  long long tot = (long long)C * gn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int col = (int)(idx / gn);
+    long long G = idx - col * gn;
+    int gy = (int)(G / g.M[0]), gx = (int)(G - (long long)gy * g.M[0]);
+    int ix = gx - g.W, iy = gy - g.W;
+    c128 v = mk<double>(0.0, 0.0);
+    if (ix >= 0 && ix < g.N[0] && iy >= 0 && iy < g.N[1]) {
+      c128 fv = f[(long long)col * g.N[0] * g.N[1] + (long long)iy * g.N[0] + ix];
+      v = mk<double>(h2 * fv.re, h2 * fv.im);
+    }
+    b[idx] = v;
+  }
+}
+hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C) {
+  long long tot = (long long)C * c->g.glob_nodes;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_rhs_from_f, dim3(blocks), dim3(256), 0, c->stream, f, b, C,
+                     c->gd, c->g.h * c->g.h, c->g.glob_nodes);
+  return hipGetLastError();
+}
+
+// r = b - S x with the global operator's coefficients formed on the fly
+__global__ void k_residual2d(const c128* b, const c128* x, c128* r, int C,
+                             const c128* al, int o_nx, int o_hx, int o_ny, int o_hy,
+                             const double* kap, GeoDev g, double h2, long long gn) {
+  const int Mx = g.M[0], My = g.M[1];
+  long long tot = (long long)C * gn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int col = (int)(idx / gn);
+    long long G = idx - col * gn;
+    int gy = (int)(G / Mx), gx = (int)(G - (long long)gy * Mx);
+    const c128* xc = x + (long long)col * gn;
+    c128 u = xc[G];
+    c128 anx = al[o_nx + gx], any = al[o_ny + gy];
+    c128 axl = any * cinv(al[o_hx + gx]);
+    c128 axr = any * cinv(al[o_hx + gx + 1]);
+    c128 ayl = anx * cinv(al[o_hy + gy]);
+    c128 ayr = anx * cinv(al[o_hy + gy + 1]);
+    int ix = min(max(gx - g.W, 0), g.N[0] - 1);
+    int iy = min(max(gy - g.W, 0), g.N[1] - 1);
+    double kk = kap[(long long)iy * g.N[0] + ix];
+    c128 J = anx * any;
+    c128 su = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im) * u;
+    c128 z = mk<double>(0.0, 0.0);
+    c128 ul = gx > 0 ? xc[G - 1] : z;
+    c128 ur = gx < Mx - 1 ? xc[G + 1] : z;
+    c128 ud = gy > 0 ? xc[G - Mx] : z;
+    c128 uu = gy < My - 1 ? xc[G + Mx] : z;
+    su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud);
+    r[idx] = b ? (b[idx] - su) : su;
+  }
+}
+hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, int C) {
+  long long tot = (long long)C * c->g.glob_nodes;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_residual2d, dim3(blocks), dim3(256), 0, c->stream, b, x, r, C,
+                     c->d_alpha_glob, c->alpha_glob_off[0], c->alpha_glob_off[1],
+                     c->alpha_glob_off[2], c->alpha_glob_off[3], c->d_kappa, c->gd,
+                     c->g.h * c->g.h, c->g.glob_nodes);
+  return hipGetLastError();
+}
+
+// per-column 2-norms, deterministic two-pass reduction
+__global__ void k_norm_part(const c128* v, long long gn, int nblk, double* part) {
+  __shared__ double sh[256];
+  int col = blockIdx.y;
+  const c128* vc = v + (long long)col * gn;
+  double s = 0.0;
+  long long chunk = (gn + nblk - 1) / nblk;
+  long long lo = (long long)blockIdx.x * chunk, hi = min(gn, lo + chunk);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    c128 z = vc[i];
+    s += z.re * z.re + z.im * z.im;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)col * nblk + blockIdx.x] = sh[0];
+}
+__global__ void k_norm_final(const double* part, int nblk, double* out) {
+  __shared__ double sh[256];
+  int col = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(long long)col * nblk + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[col] = sqrt(sh[0]);
+}
+hipError_t launch_norms(hdsw_ctx* c, const c128* v, int C, double* d_out) {
+  int nblk = c->part_blocks;
+  hipLaunchKernelGGL(k_norm_part, dim3(nblk, C), dim3(256), 0, c->stream, v,
+                     c->g.glob_nodes, nblk, c->d_part);
+  hipLaunchKernelGGL(k_norm_final, dim3(C), dim3(256), 0, c->stream, c->d_part, nblk,
+                     d_out);
+  return hipGetLastError();
+}
+
+__global__ void k_extract_interior(const c128* glob, c128* out, int C, GeoDev g,
+                                   long long gn) {
+  long long ni = (long long)g.N[0] * g.N[1];
+  long long tot = (long long)C * ni;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int col = (int)(idx / ni);
+    long long r = idx - col * ni;
+    int iy = (int)(r / g.N[0]), ix = (int)(r - (long long)iy * g.N[0]);
+    out[idx] = glob[(long long)col * gn + (long long)(iy + g.W) * g.M[0] + ix + g.W];
+  }
+}
+hipError_t launch_extract_interior(hdsw_ctx* c, const c128* glob, c128* out, int C) {
+  long long tot = (long long)C * c->g.int_nodes;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_extract_interior, dim3(blocks), dim3(256), 0, c->stream, glob,
+                     out, C, c->gd, c->g.glob_nodes);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(uint32_t* p, size_t nwords) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+hipError_t launch_zero(hdsw_ctx* c, void* p, size_t bytes) {
+  size_t nw = bytes / 4;
+  if (nw == 0) return hipSuccess;
+  int blocks = (int)std::min<size_t>((nw + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, c->stream, (uint32_t*)p, nw);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ GMRES (FP64)
+// dots[j][col] = sum_G conj(V_j[col][G]) w[col][G], two-pass deterministic
+__global__ void k_dots_part(const c128* V, int nv, const c128* w, int C, long long gn,
+                            int nblk, double* part) {
+  __shared__ double sr[256], si[256];
+  int col = blockIdx.y, j = blockIdx.z;
+  const c128* vj = V + ((long long)j * C + col) * gn;
+  const c128* wc = w + (long long)col * gn;
+  long long chunk = (gn + nblk - 1) / nblk;
+  long long lo = (long long)blockIdx.x * chunk, hi = min(gn, lo + chunk);
+  double ar = 0.0, ai = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    c128 a = vj[i], b = wc[i];
+    ar += a.re * b.re + a.im * b.im;
+    ai += a.re * b.im - a.im * b.re;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    long long o = (((long long)j * C + col) * nblk + blockIdx.x) * 2;
+    part[o] = sr[0];
+    part[o + 1] = si[0];
+  }
+}
+__global__ void k_dots_final(const double* part, int nblk, c128* out) {
+  __shared__ double sr[256], si[256];
+  long long jc = blockIdx.x;
+  double ar = 0.0, ai = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    ar += part[(jc * nblk + i) * 2];
+    ai += part[(jc * nblk + i) * 2 + 1];
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[jc] = mk<double>(sr[0], si[0]);
+}
+hipError_t launch_dots(hdsw_ctx* c, const c128* V, int nv, const c128* w, int C,
+                       c128* d_out) {
+  int nblk = c->part_blocks;
+  hipLaunchKernelGGL(k_dots_part, dim3(nblk, C, nv), dim3(256), 0, c->stream, V, nv, w,
+                     C, c->g.glob_nodes, nblk, c->d_part);
+  hipLaunchKernelGGL(k_dots_final, dim3(nv * C), dim3(256), 0, c->stream, c->d_part,
+                     nblk, d_out);
+  return hipGetLastError();
+}
+// w[col] += sign * sum_j coef[j][col] V_j[col]
+__global__ void k_axpy_multi(c128* w, const c128* V, int nv, const c128* coef, int C,
+                             long long gn, double sign) {
+  long long tot = (long long)C * gn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int col = (int)(idx / gn);
+    long long G = idx - col * gn;
+    c128 acc = mk<double>(0.0, 0.0);
+    for (int j = 0; j < nv; ++j)
+      cfma(acc, coef[(long long)j * C + col], V[((long long)j * C + col) * gn + G]);
+    c128 v = w[idx];
+    w[idx] = mk<double>(v.re + sign * acc.re, v.im + sign * acc.im);
+  }
+}
+hipError_t launch_axpy_multi(hdsw_ctx* c, c128* w, const c128* V, int nv,
+                             const c128* coef, int C, double sign) {
+  long long tot = (long long)C * c->g.glob_nodes;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_axpy_multi, dim3(blocks), dim3(256), 0, c->stream, w, V, nv, coef,
+                     C, c->g.glob_nodes, sign);
+  return hipGetLastError();
+}
+// dst[col] = src[col] * inv[col]
+__global__ void k_scale(c128* dst, const c128* src, const double* inv, int C,
+                        long long gn) {
+  long long tot = (long long)C * gn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int col = (int)(idx / gn);
+    double s = inv[col];
+    c128 v = src[idx];
+    dst[idx] = mk<double>(v.re * s, v.im * s);
+  }
+}
+hipError_t launch_scale(hdsw_ctx* c, c128* dst, const c128* src, const double* inv,
+                        int C) {
+  long long tot = (long long)C * c->g.glob_nodes;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_scale, dim3(blocks), dim3(256), 0, c->stream, dst, src, inv, C,
+                     c->g.glob_nodes);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ instantiation
+#define HDSW_INST(T)                                                                  \
+  template hipError_t launch_cast_coef<T>(hdsw_ctx*);                                \
+  template hipError_t launch_factor_block<T>(hdsw_ctx*, int);                        \
+  template hipError_t launch_fill_panel<T>(hdsw_ctx*, int, int, const int*, int,     \
+                                           const c128*, int);                        \
+  template hipError_t launch_block_solve<T>(hdsw_ctx*, int, const int*, int);        \
+  template hipError_t launch_extract_iface<T>(hdsw_ctx*, int, int, void*, long long, \
+                                              int);                                  \
+  template hipError_t launch_write_owned<T>(hdsw_ctx*, int, c128*, int);             \
+  template hipError_t launch_trace_source<T>(hdsw_ctx*, int, int, int, int);         \
+  template hipError_t launch_iface_gemm<T>(hdsw_ctx*, int, int, int, int);           \
+  template hipError_t launch_route<T>(hdsw_ctx*, int, int, int, int);
+HDSW_INST(float)
+HDSW_INST(double)
+
+}  // namespace hdsw

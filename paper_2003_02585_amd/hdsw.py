@@ -1,0 +1,202 @@
+"""Thin ctypes binding of libhdsw (include/hdsw.h), same names as the C-ABI.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch is used for device memory and streams: arrays passed
+to the device entry points are torch tensors on the GPU (complex128,
+contiguous), and the context is bound to a torch stream.
+
+If the shared library has not been built, importing this module raises;
+there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdsw.so")
+
+HDSW_OK, HDSW_EINVAL, HDSW_ENOMEM, HDSW_EDEVICE, HDSW_ENOTFACTORED, \
+    HDSW_ENOCONV, HDSW_EBUSY = range(7)
+HDSW_FP64, HDSW_MIXED = 0, 1
+KT_SOLVE, KT_GEMM, KT_FACTOR, KT_RESID = range(4)
+
+EXPORTED = [
+    "hdsw_default_options", "hdsw_setup", "hdsw_factor", "hdsw_solve",
+    "hdsw_apply_precond", "hdsw_residual", "hdsw_query", "hdsw_timing_enable",
+    "hdsw_timing_get", "hdsw_destroy", "hdsw_status_str",
+]
+
+
+class hdsw_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double)]
+
+
+class hdsw_partition(ctypes.Structure):
+    _fields_ = [("nsub", ctypes.c_int * 3)]
+
+
+class hdsw_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("rounds", ctypes.c_int),
+                ("pml_R", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("gmres_m", ctypes.c_int),
+                ("dedup", ctypes.c_int), ("hbm_budget", ctypes.c_size_t)]
+
+
+class hdsw_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+class HdswError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(
+            f"libhdsw.so not built ({path}); run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    c_void_p, c_int = ctypes.c_void_p, ctypes.c_int
+    lib.hdsw_default_options.argtypes = [ctypes.POINTER(hdsw_options)]
+    lib.hdsw_default_options.restype = None
+    lib.hdsw_setup.argtypes = [ctypes.POINTER(hdsw_grid), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(hdsw_partition), c_int,
+                               ctypes.POINTER(hdsw_options), c_void_p,
+                               ctypes.POINTER(c_void_p)]
+    lib.hdsw_setup.restype = c_int
+    lib.hdsw_factor.argtypes = [c_void_p]
+    lib.hdsw_factor.restype = c_int
+    lib.hdsw_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_int,
+                               ctypes.POINTER(hdsw_solve_info)]
+    lib.hdsw_solve.restype = c_int
+    lib.hdsw_apply_precond.argtypes = [c_void_p, c_void_p, c_void_p, c_int]
+    lib.hdsw_apply_precond.restype = c_int
+    lib.hdsw_residual.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                  ctypes.POINTER(ctypes.c_double)]
+    lib.hdsw_residual.restype = c_int
+    lib.hdsw_query.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                               ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_size_t)]
+    lib.hdsw_query.restype = c_int
+    lib.hdsw_timing_enable.argtypes = [c_void_p, c_int]
+    lib.hdsw_timing_enable.restype = c_int
+    lib.hdsw_timing_get.argtypes = [c_void_p, c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.hdsw_timing_get.restype = c_int
+    lib.hdsw_destroy.argtypes = [c_void_p]
+    lib.hdsw_destroy.restype = None
+    lib.hdsw_status_str.argtypes = [c_int]
+    lib.hdsw_status_str.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = load_library()
+
+
+def hdsw_status_str(status):
+    return _lib.hdsw_status_str(int(status)).decode()
+
+
+def _check(status, what):
+    if status != HDSW_OK:
+        raise HdswError(status, f"{what}: {hdsw_status_str(status)}")
+
+
+def hdsw_default_options(**kw):
+    o = hdsw_options()
+    _lib.hdsw_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _dev_ptr(t, what):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128
+            and t.is_contiguous()):
+        raise TypeError(f"{what} must be a contiguous complex128 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def hdsw_setup(kappa, h, nsub, pml_width, options=None, stream=None):
+    """kappa: real array [n_z][n_y][n_x] (2D: [n_y][n_x]) on the host.
+    Returns an opaque context handle (ctypes.c_void_p)."""
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    g = hdsw_grid()
+    g.dim = kappa.ndim
+    shp = list(reversed(kappa.shape)) + [1] * (3 - kappa.ndim)
+    for a in range(3):
+        g.n[a] = int(shp[a])
+    g.h = float(h)
+    p = hdsw_partition()
+    ns = list(nsub) + [1] * (3 - len(nsub))
+    for a in range(3):
+        p.nsub[a] = int(ns[a])
+    opt = options if options is not None else hdsw_default_options()
+    if stream is None:
+        s = None
+    else:
+        s = ctypes.c_void_p(int(stream))
+    ctx = ctypes.c_void_p()
+    st = _lib.hdsw_setup(ctypes.byref(g), kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         ctypes.byref(p), int(pml_width), ctypes.byref(opt), s,
+                         ctypes.byref(ctx))
+    _check(st, "hdsw_setup")
+    return ctx
+
+
+def hdsw_factor(ctx):
+    _check(_lib.hdsw_factor(ctx), "hdsw_factor")
+
+
+def hdsw_solve(ctx, f, x, nrhs, raise_on_noconv=True):
+    """f, x: complex128 GPU tensors [nrhs][interior grid].  Returns a list of
+    (iters, rel_residual) per RHS and the status."""
+    info = (hdsw_solve_info * int(nrhs))()
+    st = _lib.hdsw_solve(ctx, _dev_ptr(f, "f"), _dev_ptr(x, "x"), int(nrhs), info)
+    if st != HDSW_ENOCONV or raise_on_noconv:
+        _check(st, "hdsw_solve")
+    return [(info[i].iters, info[i].rel_residual) for i in range(nrhs)], st
+
+
+def hdsw_apply_precond(ctx, r, z, nrhs):
+    _check(_lib.hdsw_apply_precond(ctx, _dev_ptr(r, "r"), _dev_ptr(z, "z"), int(nrhs)),
+           "hdsw_apply_precond")
+
+
+def hdsw_residual(ctx, b, x, r, nrhs):
+    norms = (ctypes.c_double * int(nrhs))()
+    _check(_lib.hdsw_residual(ctx, _dev_ptr(b, "b"), _dev_ptr(x, "x"), _dev_ptr(r, "r"),
+                              int(nrhs), norms), "hdsw_residual")
+    return np.array(norms[:])
+
+
+def hdsw_query(ctx):
+    fb, ws = ctypes.c_size_t(), ctypes.c_size_t()
+    nops = ctypes.c_int()
+    _check(_lib.hdsw_query(ctx, ctypes.byref(fb), ctypes.byref(nops), ctypes.byref(ws)),
+           "hdsw_query")
+    return fb.value, nops.value, ws.value
+
+
+def hdsw_timing_enable(ctx, enable=True):
+    _check(_lib.hdsw_timing_enable(ctx, int(bool(enable))), "hdsw_timing_enable")
+
+
+def hdsw_timing_get(ctx, which):
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(_lib.hdsw_timing_get(ctx, int(which), ctypes.byref(ms), ctypes.byref(n),
+                                ctypes.byref(fl), ctypes.byref(by)), "hdsw_timing_get")
+    return ms.value, n.value, fl.value, by.value
+
+
+def hdsw_destroy(ctx):
+    if ctx:
+        _lib.hdsw_destroy(ctx)
