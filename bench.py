@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rhs", type=int, default=1)
+    ap.add_argument("--cpu-sample-rhs", type=int, default=4)
     return ap.parse_args()
 
 

@@ -91,7 +91,7 @@ typedef struct {
   double rel_residual;  /* final ||b - S x|| / ||b|| in FP64                */
 } hdsw_solve_info;
 
-/* Fills *opt with the defaults: HDSW_MIXED, rounds 1, pml_R 1e-4,
+/* Fills *opt with the defaults: HDSW_MIXED, rounds 1, pml_R 1e-16,
  * tol 1e-10, max_iter 30, gmres_m 0, dedup 1, no budget. */
 void hdsw_default_options(hdsw_options* opt);
 

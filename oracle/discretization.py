@@ -115,7 +115,7 @@ class Problem:
     In the layer the wavenumber is that of the nearest interior node (index
     clamping), the same nearest-point rule as eq. (wave_number)."""
 
-    def __init__(self, kappa, h, W, pml_R=1e-4, sigma0=None):
+    def __init__(self, kappa, h, W, pml_R=1e-16, sigma0=None):
         self.kappa = np.asarray(kappa, dtype=float)
         self.dim = self.kappa.ndim
         self.N = tuple(reversed(self.kappa.shape))

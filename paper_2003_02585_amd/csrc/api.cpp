@@ -22,7 +22,7 @@ void hdsw_default_options(hdsw_options* o) {
   if (!o) return;
   o->precision = HDSW_MIXED;
   o->rounds = 1;
-  o->pml_R = 1e-4;
+  o->pml_R = 1e-16;
   o->tol = 1e-10;
   o->max_iter = 30;
   o->gmres_m = 0;

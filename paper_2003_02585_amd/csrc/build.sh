@@ -5,11 +5,11 @@ here="$(cd "$(dirname "$0")" && pwd)"
 out="${here}/../libhdsw.so"
 flags=(-O3 -std=c++17 -fPIC --offload-arch=gfx950
        -Xclang -target-feature -Xclang -packed-fp32-ops
-       -Wall -Wno-unused-result)
+       -Wall -Wno-unused-result -Wno-pass-failed)
 objs=()
 tmp="$(mktemp -d)"
 trap 'rm -rf "$tmp"' EXIT
-for src in kernels.hip driver.cpp krylov.cpp api.cpp; do
+for src in kernels.hip mfma.hip driver.cpp krylov.cpp api.cpp; do
   o="${tmp}/${src%.*}.o"
   hipcc "${flags[@]}" -x hip -c "${here}/${src}" -o "$o" &
   objs+=("$o")

@@ -264,7 +264,10 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   g.int_nodes = nint;
   g.n = g.ne[0];
   g.K = g.ne[1];
-  if (g.n > 512) {  // one x-line per block; the block solver keeps a row per lane
+  g.nP = (g.n + 15) / 16 * 16;
+  g.mid = g.K / 2;
+  // the block solver keeps an nP-long vector per column in LDS
+  if (g.nP > (opt->precision == HDSW_MIXED ? 512 : 256)) {
     delete c;
     return HDSW_EINVAL;
   }
@@ -302,6 +305,8 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   d.K = g.K;
   d.NI = g.NI;
   d.nsub = g.nsub;
+  d.nP = g.nP;
+  d.mid = g.mid;
   for (int a = 0; a < 3; ++a) {
     d.N[a] = g.N[a];
     d.P[a] = g.P[a];
@@ -378,7 +383,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   hdsw_status st;
   size_t e = elt(c);
   c->coef_stride = (size_t)g.K * (g.n + 1) + (size_t)(g.K + 1) * g.n + (size_t)g.K * g.n;
-  size_t xbytes = (size_t)c->nops * g.K * g.n * g.n * e;
+  size_t xbytes = (size_t)c->nops * g.K * g.nP * g.nP * e;
   size_t tbytes = (size_t)c->nops * g.NI * g.NI * e;
   c->factor_bytes = xbytes + tbytes;
   void* p;
@@ -436,12 +441,15 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
     double fl = 8.0 * g.n * (double)g.n * g.n * g.K * c->nops;
     double by = 2.0 * g.K * (double)g.n * g.n * sizeof(cpx<T>) * c->nops;
     TimedScope ts(c, KT_FACTOR, fl, by);
-    for (int k = 0; k < g.K; ++k) HCHK(launch_factor_block<T>(c, k));
+    // twisted: top and bottom chains advance together, then the middle line
+    int steps = std::max(g.mid, g.K - 1 - g.mid);
+    for (int st = 0; st < steps; ++st) HCHK(launch_factor_step<T>(c, st, 0));
+    HCHK(launch_factor_step<T>(c, 0, 1));
   }
   // interface-to-interface response T = P_I S^{-1} P_I^T of every distinct
   // operator: block solves with unit sources on the interface dofs
   const size_t e = sizeof(cpx<T>);
-  size_t per_col = (size_t)g.K * g.n * e;
+  size_t per_col = (size_t)(g.K + 1) * g.n * e;
   size_t budget = (size_t)1 << 31;
   int ct = (int)std::min<size_t>(g.NI, std::max<size_t>(1, budget / per_col));
   void* tmp = nullptr;
@@ -504,7 +512,7 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     dst = decltype(dst)(p);               \
   } while (0)
     size_t iface = (size_t)g.nsub * C * g.NI * e;
-    WALLOC(c->d_panel, (size_t)g.nsub * g.K * C * g.n * e);
+    WALLOC(c->d_panel, (size_t)g.nsub * (g.K + 1) * C * g.n * e);
     WALLOC(c->d_slots, iface * c->sch.nsweeps);
     WALLOC(c->d_g, iface);
     WALLOC(c->d_accg, iface);
@@ -598,7 +606,7 @@ static size_t max_cols(hdsw_ctx* c) {
   if (!c->opt.hbm_budget) return 1u << 30;
   const Geometry& g = c->g;
   size_t e = elt(c);
-  size_t per_col = (size_t)g.nsub * g.K * g.n * e +
+  size_t per_col = (size_t)g.nsub * (g.K + 1) * g.n * e +
                    (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + 4) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);

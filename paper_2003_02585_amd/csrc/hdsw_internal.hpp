@@ -85,6 +85,8 @@ struct Geometry {
   // 2D block structure: x-lines (n = ne[0]) indexed by y (K = ne[1]).
   // 3D block structure: xy-planes (n = ne[0] ne[1]) indexed by z (K = ne[2]).
   int n = 1, K = 1;
+  int nP = 16;                 // n rounded up to a multiple of 16 (MFMA tiles)
+  int mid = 0;                 // middle line of the twisted factorization
   long long sub_nodes = 1;     // nodes of one extended subdomain
   long long glob_nodes = 1;    // nodes of the global grid
   long long int_nodes = 1;     // interior nodes
@@ -104,7 +106,7 @@ struct Geometry {
 
 // Device-side view of the geometry (plain struct passed by value).
 struct GeoDev {
-  int dim, W, n, K, NI, nsub;
+  int dim, W, n, K, NI, nsub, nP, mid;
   int N[3], P[3], na[3], ne[3], M[3];
   int side_len[6], side_off[6];
 };
@@ -173,13 +175,13 @@ struct hdsw_ctx {
   int* d_flag = nullptr;            // device error flag (singular pivot)
 
   // precision-dependent factors: element type cpx<float> or cpx<double>
-  void* d_X = nullptr;              // [nops][K][n][n] column-major blocks
+  void* d_X = nullptr;              // [nops][K][nP][nP] column-major blocks
   void* d_T = nullptr;              // [nops][NI][NI] column-major (2D)
   void* d_coefT = nullptr;          // coefficients in working precision
 
   // workspaces sized for Cmax columns
   int Cmax = 0;
-  void* d_panel = nullptr;          // [nsub][K][C][n]
+  void* d_panel = nullptr;          // [nsub][K+1][C][n] (line K: scratch)
   void* d_slots = nullptr;          // [nsweeps][nsub][C][NI]
   void* d_g = nullptr;              // [nsub][C][NI] trace sources of a step
   void* d_accg = nullptr;           // [nsub][C][NI] accumulated sources
@@ -209,7 +211,7 @@ hipError_t launch_assemble(hdsw_ctx* c);
 template <class T>
 hipError_t launch_cast_coef(hdsw_ctx* c);
 template <class T>
-hipError_t launch_factor_block(hdsw_ctx* c, int k);
+hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle);
 template <class T>
 hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids,
                              int C, const c128* rglob, int unit_col0);

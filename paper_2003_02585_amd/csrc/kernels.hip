@@ -128,136 +128,7 @@ hipError_t launch_cast_coef(hdsw_ctx* c) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ factor
-// One block row of the block-tridiagonal LU of every distinct operator:
-//   D_k = A_k - B_k X_{k-1} B_k  (B_k = diag of the y-faces between lines
-//   k-1 and k), then X_k = D_k^{-1} by in-place Gauss-Jordan elimination
-//   with partial pivoting (largest |re|+|im| in the pivot column, lowest
-//   row index on ties).  The matrix is handled in its transposed row-major
-//   form, so the inverse lands column-major.  One workgroup per operator.
-template <class T>
-__global__ __launch_bounds__(1024) void k_factor_block(cpx<T>* X, size_t xstride,
-                                                       const cpx<T>* coefT,
-                                                       size_t cstride, GeoDev g,
-                                                       int k, int* flag, int nops) {
-  extern __shared__ unsigned char smem_raw[];
-  int op = blockIdx.x;
-  if (op >= nops) return;
-  const int n = g.n, K = g.K;
-  const int tid = threadIdx.x, bs = blockDim.x;
-  cpx<T>* rowv = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* colv = rowv + n;
-  int* perm = reinterpret_cast<int*>(colv + n);
-  T* redv = reinterpret_cast<T*>(perm + ((n + 3) & ~3));
-  int* redi = reinterpret_cast<int*>(redv + bs);
-
-  cpx<T>* M = X + (size_t)op * xstride + (size_t)k * n * n;
-  const cpx<T>* prev = k > 0 ? M - (size_t)n * n : nullptr;
-  const cpx<T>* ax = coefT + (size_t)op * cstride + (size_t)k * (n + 1);
-  const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1) + (size_t)k * n;
-  const cpx<T>* dg = coefT + (size_t)op * cstride + (size_t)K * (n + 1) +
-                     (size_t)(K + 1) * n + (size_t)k * n;
-  // build D_k (symmetric: its transpose has the same formula)
-  for (int idx = tid; idx < n * n; idx += bs) {
-    int i = idx / n, j = idx - i * n;
-    cpx<T> v = mk<T>(T(0), T(0));
-    if (i == j) v = dg[i];
-    else if (j == i + 1) v = ax[j];
-    else if (i == j + 1) v = ax[i];
-    if (prev) v = v - ay[i] * ay[j] * prev[idx];
-    M[idx] = v;
-  }
-  __threadfence_block();
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    // pivot search in column j, rows j..n-1
-    T best = T(-1);
-    int bi = n;
-    for (int i = j + tid; i < n; i += bs) {
-      cpx<T> a = M[(size_t)i * n + j];
-      T m = fabs(a.re) + fabs(a.im);
-      if (m > best) { best = m; bi = i; }
-    }
-    redv[tid] = best;
-    redi[tid] = bi;
-    __syncthreads();
-    for (int s = bs / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        T ob = redv[tid + s];
-        int oi = redi[tid + s];
-        if (ob > redv[tid] || (ob == redv[tid] && oi < redi[tid])) {
-          redv[tid] = ob;
-          redi[tid] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    int p = redi[0];
-    if (p >= n) p = j;
-    if (tid == 0) perm[j] = p;
-    if (p != j) {
-      for (int jj = tid; jj < n; jj += bs) {
-        cpx<T> a = M[(size_t)j * n + jj];
-        M[(size_t)j * n + jj] = M[(size_t)p * n + jj];
-        M[(size_t)p * n + jj] = a;
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
-    cpx<T> piv = M[(size_t)j * n + j];
-    if (piv.re == T(0) && piv.im == T(0)) {
-      if (tid == 0) atomicExch(flag, 1);
-    }
-    cpx<T> inv = cinv(piv);
-    for (int jj = tid; jj < n; jj += bs) rowv[jj] = (jj == j) ? inv : M[(size_t)j * n + jj] * inv;
-    for (int i = tid; i < n; i += bs) colv[i] = M[(size_t)i * n + j];
-    __syncthreads();
-    for (int idx = tid; idx < n * n; idx += bs) {
-      int i = idx / n, jj = idx - i * n;
-      if (i == j) {
-        M[idx] = rowv[jj];
-      } else if (jj == j) {
-        M[idx] = -(colv[i] * inv);
-      } else {
-        cpx<T> m = M[idx];
-        cpx<T> cv = colv[i], rv = rowv[jj];
-        m.re = fma(-cv.re, rv.re, m.re);
-        m.re = fma(cv.im, rv.im, m.re);
-        m.im = fma(-cv.re, rv.im, m.im);
-        m.im = fma(-cv.im, rv.re, m.im);
-        M[idx] = m;
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
-  }
-  // undo the row interchanges as column interchanges, last first
-  for (int j = n - 1; j >= 0; --j) {
-    int p = perm[j];
-    if (p != j) {
-      for (int i = tid; i < n; i += bs) {
-        cpx<T> a = M[(size_t)i * n + j];
-        M[(size_t)i * n + j] = M[(size_t)i * n + p];
-        M[(size_t)i * n + p] = a;
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
-  }
-}
-
-template <class T>
-hipError_t launch_factor_block(hdsw_ctx* c, int k) {
-  const Geometry& g = c->g;
-  int bs = 1024;
-  size_t lds = 2 * g.n * sizeof(cpx<T>) + ((g.n + 3) & ~3) * sizeof(int) +
-               bs * (sizeof(T) + sizeof(int));
-  size_t xstride = (size_t)g.K * g.n * g.n;
-  hipLaunchKernelGGL(k_factor_block<T>, dim3(c->nops), dim3(bs), lds, c->stream,
-                     (cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
-                     c->coef_stride, c->gd, k, c->d_flag, c->nops);
-  return hipGetLastError();
-}
+// (factorization kernels: mfma.hip)
 
 // ------------------------------------------------------------ panels
 // mode 0: owned part of a global FP64 vector, cast to the working precision
@@ -275,6 +146,7 @@ __global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch
        idx += (long long)gridDim.x * blockDim.x) {
     int b = (int)(idx / per);
     long long r = idx - b * per;
+    cpx<T>* dst = panel + (long long)b * (K + 1) * C * n + r;
     int k = (int)(r / ((long long)C * n));
     int rem = (int)(r - (long long)k * C * n);
     int col = rem / n, p = rem - col * n;
@@ -296,7 +168,7 @@ __global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch
         if (dy >= 0) v = v + a[dy];
       }
     }
-    panel[idx] = v;
+    *dst = v;
   }
 }
 
@@ -311,139 +183,7 @@ hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ block solve
-// Batched multi-RHS block-tridiagonal solve with the stored inverses:
-//   forward   w_0 = X_0 f_0,  w_k = X_k (f_k - B_k w_{k-1})
-//   backward  x_{K-1} = w_{K-1},  x_k = w_k - X_k (B_{k+1} x_{k+1})
-// One workgroup per (batch entry, tile of CT columns); each thread owns up
-// to RPT rows and keeps CT complex accumulators per row.  The vector being
-// multiplied sits in LDS and is read as a broadcast; X_k is streamed with
-// consecutive rows in consecutive lanes.
-template <class T, int CT, int RPT>
-__global__ __launch_bounds__(256) void k_block_solve(const cpx<T>* __restrict__ X,
-                                                     size_t xstride,
-                                                     const cpx<T>* __restrict__ coefT,
-                                                     size_t cstride,
-                                                     cpx<T>* __restrict__ panel,
-                                                     const int* __restrict__ ops, GeoDev g,
-                                                     int C, int nbatch) {
-  extern __shared__ unsigned char smem_raw[];
-  const int n = g.n, K = g.K;
-  const int b = blockIdx.y;
-  if (b >= nbatch) return;
-  const int c0 = blockIdx.x * CT;
-  const int nc = min(CT, C - c0);
-  const int op = ops[b];
-  const int tid = threadIdx.x;
-  cpx<T>* v = reinterpret_cast<cpx<T>*>(smem_raw);    // [CT][n]
-  cpx<T>* w = v + CT * n;                              // [CT][n]
-  const cpx<T>* Xo = X + (size_t)op * xstride;
-  const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
-  cpx<T>* pb = panel + (size_t)b * K * C * n;
-
-  cpx<T> acc[RPT][CT];
-  for (int k = 0; k < K; ++k) {
-    for (int idx = tid; idx < CT * n; idx += 256) {
-      int cc = idx / n, r = idx - cc * n;
-      cpx<T> val = mk<T>(T(0), T(0));
-      if (cc < nc) val = pb[((size_t)k * C + c0 + cc) * n + r];
-      if (k > 0) val = val - ay[(size_t)k * n + r] * w[cc * n + r];
-      v[idx] = val;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-#pragma unroll
-      for (int cc = 0; cc < CT; ++cc) acc[q][cc] = mk<T>(T(0), T(0));
-    const cpx<T>* Xk = Xo + (size_t)k * n * n;
-    for (int j = 0; j < n; ++j) {
-      cpx<T> vj[CT];
-#pragma unroll
-      for (int cc = 0; cc < CT; ++cc) vj[cc] = v[cc * n + j];
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        int r = tid + q * 256;
-        if (r < n) {
-          cpx<T> x = Xk[(size_t)j * n + r];
-#pragma unroll
-          for (int cc = 0; cc < CT; ++cc) cfma(acc[q][cc], x, vj[cc]);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      int r = tid + q * 256;
-      if (r < n) {
-#pragma unroll
-        for (int cc = 0; cc < CT; ++cc) {
-          if (cc < nc) pb[((size_t)k * C + c0 + cc) * n + r] = acc[q][cc];
-          w[cc * n + r] = acc[q][cc];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int k = K - 2; k >= 0; --k) {
-    for (int idx = tid; idx < CT * n; idx += 256) {
-      int r = idx % n;
-      v[idx] = ay[(size_t)(k + 1) * n + r] * w[idx];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-#pragma unroll
-      for (int cc = 0; cc < CT; ++cc) acc[q][cc] = mk<T>(T(0), T(0));
-    const cpx<T>* Xk = Xo + (size_t)k * n * n;
-    for (int j = 0; j < n; ++j) {
-      cpx<T> vj[CT];
-#pragma unroll
-      for (int cc = 0; cc < CT; ++cc) vj[cc] = v[cc * n + j];
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        int r = tid + q * 256;
-        if (r < n) {
-          cpx<T> x = Xk[(size_t)j * n + r];
-#pragma unroll
-          for (int cc = 0; cc < CT; ++cc) cfma(acc[q][cc], x, vj[cc]);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      int r = tid + q * 256;
-      if (r < n) {
-#pragma unroll
-        for (int cc = 0; cc < CT; ++cc) {
-          cpx<T> wk = mk<T>(T(0), T(0));
-          if (cc < nc) wk = pb[((size_t)k * C + c0 + cc) * n + r];
-          cpx<T> xk = wk - acc[q][cc];
-          if (cc < nc) pb[((size_t)k * C + c0 + cc) * n + r] = xk;
-          w[cc * n + r] = xk;
-        }
-      }
-    }
-    __syncthreads();
-  }
-}
-
-template <class T>
-hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
-  const Geometry& g = c->g;
-  if (g.n > 512) return hipErrorInvalidValue;
-  constexpr int CT = 4;
-  dim3 grid((C + CT - 1) / CT, nbatch);
-  size_t lds = 2 * CT * g.n * sizeof(cpx<T>);
-  size_t xstride = (size_t)g.K * g.n * g.n;
-  if (g.n <= 256)
-    hipLaunchKernelGGL((k_block_solve<T, CT, 1>), grid, dim3(256), lds, c->stream,
-                       (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
-                       c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
-  else
-    hipLaunchKernelGGL((k_block_solve<T, CT, 2>), grid, dim3(256), lds, c->stream,
-                       (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
-                       c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
-  return hipGetLastError();
-}
+// (block solve kernels: mfma.hip)
 
 // ------------------------------------------------------------ interface I/O
 // dst[b][col][i] = panel[b][k_i][col][p_i]  (restriction P_I)
@@ -459,7 +199,7 @@ __global__ void k_extract_iface(const cpx<T>* panel, int nbatch, int C, cpx<T>* 
     int p, k;
     dof_node2d(g, i, p, k);
     dst[b * dst_sb + (long long)col * dst_ld + i] =
-        panel[(((long long)b * g.K + k) * C + col) * g.n + p];
+        panel[(((long long)b * (g.K + 1) + k) * C + col) * g.n + p];
   }
 }
 template <class T>
@@ -491,7 +231,7 @@ __global__ void k_write_owned(const cpx<T>* panel, int C, c128* glob, long long 
     int bx = s % g.P[0], by = s / g.P[0];
     if (!(owned_axis(g, 0, bx, p) && owned_axis(g, 1, by, k))) continue;
     long long G = (long long)(by * g.na[1] + k) * g.M[0] + (bx * g.na[0] + p);
-    c128 v = ccast<double>(panel[idx]);
+    c128 v = ccast<double>(panel[(long long)s * (K + 1) * C * n + r]);
     c128* dst = glob + (long long)col * gn + G;
     *dst = accumulate ? (*dst + v) : v;
   }
@@ -557,62 +297,7 @@ hipError_t launch_trace_source(hdsw_ctx* c, int L, int off, int cnt, int C) {
   return hipGetLastError();
 }
 
-// out[s][col][:] = T_op(s) * g[s][col][:] (+ y[s][col][:])
-// the subdomain solve of one sweep step restricted to its interface layers
-template <class T, int CT>
-__global__ __launch_bounds__(256) void k_iface_gemm(const cpx<T>* __restrict__ Tm,
-                                                    const cpx<T>* __restrict__ gbuf,
-                                                    const cpx<T>* __restrict__ ybuf,
-                                                    cpx<T>* __restrict__ out,
-                                                    const int* op_of, const int* subs,
-                                                    int C, int NI, int add_y) {
-  __shared__ cpx<T> vs[CT][256];
-  const int s = subs[blockIdx.z];
-  const int c0 = blockIdx.y * CT;
-  const int nc = min(CT, C - c0);
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  const cpx<T>* Top = Tm + (size_t)op_of[s] * NI * NI;
-  const cpx<T>* gb = gbuf + ((size_t)s * C + c0) * NI;
-  cpx<T> acc[CT];
-#pragma unroll
-  for (int cc = 0; cc < CT; ++cc) acc[cc] = mk<T>(T(0), T(0));
-  for (int j0 = 0; j0 < NI; j0 += 256) {
-    int jn = min(256, NI - j0);
-    __syncthreads();
-#pragma unroll
-    for (int cc = 0; cc < CT; ++cc) {
-      int j = threadIdx.x;
-      vs[cc][j] = (cc < nc && j < jn) ? gb[(size_t)cc * NI + j0 + j] : mk<T>(T(0), T(0));
-    }
-    __syncthreads();
-    if (row < NI) {
-      for (int j = 0; j < jn; ++j) {
-        cpx<T> x = Top[(size_t)(j0 + j) * NI + row];
-#pragma unroll
-        for (int cc = 0; cc < CT; ++cc) cfma(acc[cc], x, vs[cc][j]);
-      }
-    }
-  }
-  if (row < NI) {
-    for (int cc = 0; cc < nc; ++cc) {
-      size_t o = ((size_t)s * C + c0 + cc) * NI + row;
-      cpx<T> v = acc[cc];
-      if (add_y) v = v + ybuf[o];
-      out[o] = v;
-    }
-  }
-}
-template <class T>
-hipError_t launch_iface_gemm(hdsw_ctx* c, int off, int cnt, int C, int add_y) {
-  constexpr int CT = 8;
-  int NI = c->g.NI;
-  dim3 grid((NI + 255) / 256, (C + CT - 1) / CT, cnt);
-  hipLaunchKernelGGL((k_iface_gemm<T, CT>), grid, dim3(256), 0, c->stream,
-                     (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_g,
-                     (const cpx<T>*)c->d_y, (cpx<T>*)c->d_out, c->d_op_of_sub,
-                     c->d_step_subs + off, C, NI, add_y);
-  return hipGetLastError();
-}
+// (interface GEMM: mfma.hip)
 
 // Route the traces of one step to the neighbours' slots (Algorithm 2.1:
 // add the transferred trace to the l'-th local trace of the neighbour).
@@ -919,15 +604,12 @@ hipError_t launch_scale(hdsw_ctx* c, c128* dst, const c128* src, const double* i
 // ------------------------------------------------------------ instantiation
 #define HDSW_INST(T)                                                                  \
   template hipError_t launch_cast_coef<T>(hdsw_ctx*);                                \
-  template hipError_t launch_factor_block<T>(hdsw_ctx*, int);                        \
   template hipError_t launch_fill_panel<T>(hdsw_ctx*, int, int, const int*, int,     \
                                            const c128*, int);                        \
-  template hipError_t launch_block_solve<T>(hdsw_ctx*, int, const int*, int);        \
   template hipError_t launch_extract_iface<T>(hdsw_ctx*, int, int, void*, long long, \
                                               int);                                  \
   template hipError_t launch_write_owned<T>(hdsw_ctx*, int, c128*, int);             \
   template hipError_t launch_trace_source<T>(hdsw_ctx*, int, int, int, int);         \
-  template hipError_t launch_iface_gemm<T>(hdsw_ctx*, int, int, int, int);           \
   template hipError_t launch_route<T>(hdsw_ctx*, int, int, int, int);
 HDSW_INST(float)
 HDSW_INST(double)

@@ -36,7 +36,7 @@ def test_status_strings_and_defaults():
         assert H.hdsw_status_str(s).startswith("HDSW")
     o = H.hdsw_default_options()
     assert (o.precision, o.rounds, o.gmres_m, o.dedup) == (H.HDSW_MIXED, 1, 0, 1)
-    assert o.pml_R == 1e-4 and o.tol == 1e-10
+    assert o.pml_R == 1e-16 and o.tol == 1e-10
 
 
 @pytest.mark.parametrize("bad", [

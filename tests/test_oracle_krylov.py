@@ -11,12 +11,12 @@ import oracle as O
 from paper_2003_02585_amd import workloads as wl
 
 
-def _setup(layer=None, N=64, P=(4, 4)):
+def _setup(layer=None, N=64, P=(4, 4), pml_R=1e-16):
     h = 1.0 / N
     k = 2 * np.pi / (10 * h)
     kap = wl.constant_kappa((N, N), k) if layer is None else \
         wl.two_layer_kappa((N, N), h, k, layer * k, 0.37)
-    prob = O.Problem(kap, h, 16)
+    prob = O.Problem(kap, h, 16, pml_R=pml_R)
     part = O.Partition(prob, P)
     sol = O.SubdomainSolvers(part)
     S = O.global_operator(prob)
@@ -58,7 +58,7 @@ def test_gmres_two_layer_matches_direct_solve():
 
 def test_gmres_identity_preconditioner_small_dense():
     # GMRES itself against a dense solve on a tiny system
-    prob, part, sol, S, b = _setup(N=16, P=(2, 2))
+    prob, part, sol, S, b = _setup(N=16, P=(2, 2), pml_R=1e-4)
     x, hist = O.gmres(S, b, lambda r: r, m=30, tol=1e-12, maxit=2000)
     ref = np.linalg.solve(S.toarray(), b.ravel())
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
