@@ -107,6 +107,12 @@ static void build_schedule(hdsw_ctx* c) {
       }
     }
   }
+  s.in_active.assign(s.nsweeps * 6, 0);
+  for (int L0 = 0; L0 < s.nsweeps; ++L0)
+    for (int f = 0; f < 2 * g.dim; ++f) {
+      int lq = s.lprime[L0 * 6 + f];
+      if (lq >= 0) s.in_active[lq * 6 + (f ^ 1)] = 1;
+    }
 }
 
 // ------------------------------------------------------------ PML profile
@@ -175,53 +181,66 @@ static size_t elt(const hdsw_ctx* c) {
 }
 
 // ------------------------------------------------------------ timing
+// Pairs of HIP events from a pool created once per context bracket the
+// timed launches on the context's stream; they are resolved when the
+// timings are read.
 struct PendingEv {
   int cls;
-  hipEvent_t a, b;
+  int slot;
   double flops, bytes;
 };
-static std::unordered_map<const hdsw_ctx*, std::vector<PendingEv>>& pending() {
-  static std::unordered_map<const hdsw_ctx*, std::vector<PendingEv>> m;
+struct EvPool {
+  std::vector<hipEvent_t> ev;      // 2 per slot
+  std::vector<PendingEv> pending;
+  size_t next = 0;
+};
+static std::unordered_map<const hdsw_ctx*, EvPool>& pools() {
+  static std::unordered_map<const hdsw_ctx*, EvPool> m;
   return m;
 }
+static void resolve_timing(hdsw_ctx* c);
 struct TimedScope {
   hdsw_ctx* c;
   int cls;
   double flops, bytes;
-  hipEvent_t a = nullptr;
+  int slot = -1;
   TimedScope(hdsw_ctx* c_, int cls_, double f, double b) : c(c_), cls(cls_), flops(f), bytes(b) {
-    if (c->tm.on) {
-      if (hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, c->stream);
-      else a = nullptr;
+    if (!c->tm.on) return;
+    EvPool& p = pools()[c];
+    if (p.ev.empty()) {
+      p.ev.resize(2 * 8192, nullptr);
+      for (auto& e : p.ev)
+        if (hipEventCreate(&e) != hipSuccess) e = nullptr;
     }
+    if (p.next >= p.ev.size() / 2) resolve_timing(c);
+    slot = (int)p.next++;
+    if (p.ev[2 * slot]) (void)hipEventRecord(p.ev[2 * slot], c->stream);
   }
   ~TimedScope() {
-    if (c->tm.on && a) {
-      hipEvent_t b = nullptr;
-      if (hipEventCreate(&b) == hipSuccess) {
-        (void)hipEventRecord(b, c->stream);
-        pending()[c].push_back({cls, a, b, flops, bytes});
-      } else {
-        (void)hipEventDestroy(a);
-      }
-    }
+    if (slot < 0) return;
+    EvPool& p = pools()[c];
+    if (p.ev[2 * slot + 1]) (void)hipEventRecord(p.ev[2 * slot + 1], c->stream);
+    p.pending.push_back({cls, slot, flops, bytes});
   }
 };
 
 static void resolve_timing(hdsw_ctx* c) {
-  auto& v = pending()[c];
-  for (auto& e : v) {
+  auto it = pools().find(c);
+  if (it == pools().end()) return;
+  EvPool& p = it->second;
+  for (auto& e : p.pending) {
+    hipEvent_t a = p.ev[2 * e.slot], b = p.ev[2 * e.slot + 1];
     float ms = 0.f;
-    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+    if (a && b && hipEventSynchronize(b) == hipSuccess &&
+        hipEventElapsedTime(&ms, a, b) == hipSuccess) {
       c->tm.ms[e.cls] += ms;
       c->tm.launches[e.cls] += 1;
       c->tm.flops[e.cls] += e.flops;
       c->tm.bytes[e.cls] += e.bytes;
     }
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
   }
-  v.clear();
+  p.pending.clear();
+  p.next = 0;
 }
 
 // ------------------------------------------------------------ setup
@@ -267,7 +286,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   g.nP = (g.n + 15) / 16 * 16;
   g.mid = g.K / 2;
   // the block solver keeps an nP-long vector per column in LDS
-  if (g.nP > (opt->precision == HDSW_MIXED ? 512 : 256)) {
+  if (g.nP > 256) {
     delete c;
     return HDSW_EINVAL;
   }
@@ -397,6 +416,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   SALLOC(c->d_T, tbytes);
   SALLOC(c->d_coef, c->coef_stride * c->nops * sizeof(c128));
   SALLOC(c->d_coefT, c->coef_stride * c->nops * e);
+  SALLOC(c->d_cface, (size_t)c->nops * (g.NI / 2) * e);
   SALLOC(c->d_kappa_sub, (size_t)c->nops * g.sub_nodes * sizeof(double));
   SALLOC(c->d_kappa, (size_t)nint * sizeof(double));
   SALLOC(c->d_alpha_sub, al_sub.size() * sizeof(c128));
@@ -437,6 +457,7 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
   HCHK(launch_zero(c, c->d_flag, sizeof(int)));
   HCHK(launch_assemble(c));
   HCHK(launch_cast_coef<T>(c));
+  HCHK(launch_face_coef<T>(c));
   {
     double fl = 8.0 * g.n * (double)g.n * g.n * g.K * c->nops;
     double by = 2.0 * g.K * (double)g.n * g.n * sizeof(cpx<T>) * c->nops;
@@ -496,10 +517,10 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   if (C > c->Cmax) {
-    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_out, c->d_y,
+    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_y,
                     c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
     for (void* p : ptrs) dev_free(c, p);
-    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_out = c->d_y = nullptr;
+    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_y = nullptr;
     c->d_xg = c->d_rg = c->d_bg = nullptr;
     c->d_part = c->d_norm = nullptr;
     c->Cmax = 0;
@@ -514,9 +535,8 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     size_t iface = (size_t)g.nsub * C * g.NI * e;
     WALLOC(c->d_panel, (size_t)g.nsub * (g.K + 1) * C * g.n * e);
     WALLOC(c->d_slots, iface * c->sch.nsweeps);
-    WALLOC(c->d_g, iface);
+    WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) * g.NI * e);
     WALLOC(c->d_accg, iface);
-    WALLOC(c->d_out, iface);
     WALLOC(c->d_y, iface);
     WALLOC(c->d_xg, (size_t)C * g.glob_nodes * sizeof(c128));
     WALLOC(c->d_rg, (size_t)C * g.glob_nodes * sizeof(c128));
@@ -573,14 +593,17 @@ static hdsw_status ddm_impl(hdsw_ctx* c, const c128* r, c128* out, int C, int ac
     for (int st = 0; st < s.nsteps; ++st) {
       int off = s.step_off[L * s.nsteps + st], cnt = s.step_cnt[L * s.nsteps + st];
       if (cnt == 0) continue;
-      HCHK(launch_trace_source<T>(c, L, off, cnt, C));
       {
-        double fl = 8.0 * g.NI * (double)g.NI * C * cnt;
-        double by = (double)g.NI * g.NI * e * std::min(cnt, c->nops) + 3.0 * g.NI * C * e * cnt;
+        double nin = 0, nout = 0;
+        for (int f = 0; f < 2 * g.dim; ++f) {
+          if (s.in_active[L * 6 + f]) nin += 2 * g.side_len[f];
+          if (s.lprime[L * 6 + f] >= 0) nout += 2 * g.side_len[f];
+        }
+        double fl = 8.0 * nin * nout * C * cnt;
+        double by = nin * nout * e * std::min(cnt, c->nops) + (nin + 2 * nout) * C * e * cnt;
         TimedScope ts(c, KT_GEMM, fl, by);
-        HCHK(launch_iface_gemm<T>(c, off, cnt, C, L == 0 ? 1 : 0));
+        HCHK(launch_sweep_step<T>(c, L, off, cnt, C));
       }
-      HCHK(launch_route<T>(c, L, off, cnt, C));
     }
   }
   HCHK(launch_fill_panel<T>(c, 1, g.nsub, c->d_all_subs, C, r, 0));
@@ -607,7 +630,7 @@ static size_t max_cols(hdsw_ctx* c) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   size_t per_col = (size_t)g.nsub * (g.K + 1) * g.n * e +
-                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + 4) +
+                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + 2) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
   size_t used = c->alloc_bytes;
@@ -738,7 +761,12 @@ hdsw_status timing_get(hdsw_ctx* c, int which, double* ms, long long* n, double*
 void destroy(hdsw_ctx* c) {
   if (!c) return;
   resolve_timing(c);
-  pending().erase(c);
+  auto it = pools().find(c);
+  if (it != pools().end()) {
+    for (auto& e : it->second.ev)
+      if (e) (void)hipEventDestroy(e);
+    pools().erase(it);
+  }
   for (auto& b : c->bufs) (void)hipFree(b.p);
   delete c;
 }

@@ -123,6 +123,9 @@ struct Schedule {
   // lprime[L * 6 + face] = sweep that uses a trace generated in sweep L
   // across face (0:-x,1:+x,2:-y,3:+y,4:-z,5:+z); -1 = dropped
   std::vector<int> lprime;
+  // in_active[L * 6 + face] = 1 if the face can hold a received trace in
+  // sweep L (some sweep L0 <= L routes a trace across it into slot L)
+  std::vector<int> in_active;
 };
 
 // ---------------------------------------------------------------- buffers
@@ -178,14 +181,14 @@ struct hdsw_ctx {
   void* d_X = nullptr;              // [nops][K][nP][nP] column-major blocks
   void* d_T = nullptr;              // [nops][NI][NI] column-major (2D)
   void* d_coefT = nullptr;          // coefficients in working precision
+  void* d_cface = nullptr;          // [nops][NI/2] face coupling per face and t
 
   // workspaces sized for Cmax columns
   int Cmax = 0;
   void* d_panel = nullptr;          // [nsub][K+1][C][n] (line K: scratch)
   void* d_slots = nullptr;          // [nsweeps][nsub][C][NI]
-  void* d_g = nullptr;              // [nsub][C][NI] trace sources of a step
+  void* d_g = nullptr;              // [nsub][Cp/8][NI][8] sources of a step
   void* d_accg = nullptr;           // [nsub][C][NI] accumulated sources
-  void* d_out = nullptr;            // [nsub][C][NI] interface outputs
   void* d_y = nullptr;              // [nsub][C][NI] source-driven outputs
   hdsw::c128* d_xg = nullptr;       // [C][glob] iterate (FP64)
   hdsw::c128* d_rg = nullptr;       // [C][glob] residual (FP64)
@@ -224,11 +227,9 @@ hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
 template <class T>
 hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate);
 template <class T>
-hipError_t launch_trace_source(hdsw_ctx* c, int L, int off, int cnt, int C);
+hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C);
 template <class T>
-hipError_t launch_iface_gemm(hdsw_ctx* c, int off, int cnt, int C, int add_y);
-template <class T>
-hipError_t launch_route(hdsw_ctx* c, int L, int off, int cnt, int C);
+hipError_t launch_face_coef(hdsw_ctx* c);
 hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C);
 hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r,
                            int C);

@@ -246,112 +246,6 @@ hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ sweep step
-// Trace -> source (the discrete potential): for a pair received on a face,
-//   g[layer 1] =  c * pair[layer 0],   g[layer 0] = -c * pair[layer 1],
-// c = the receiver's coefficient across that face (= [S_r, chi_r] v).
-// Also accumulates the sources of every sweep for the final owned solve.
-template <class T>
-__global__ void k_trace_source(const cpx<T>* slots, cpx<T>* gbuf, cpx<T>* accg,
-                               const cpx<T>* coefT, size_t cstride, const int* op_of,
-                               const int* subs, int cnt, int L, int C, GeoDev g) {
-  const int NI = g.NI, n = g.n, K = g.K;
-  long long tot = (long long)cnt * C * NI;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int bi = (int)(idx / ((long long)C * NI));
-    int r = (int)(idx - (long long)bi * C * NI);
-    int col = r / NI, i = r - col * NI;
-    int s = subs[bi];
-    int side = 0;
-    while (side < 3 && i >= g.side_off[side + 1]) ++side;
-    int len = g.side_len[side];
-    int rr = i - g.side_off[side];
-    int lay = rr / len, t = rr - lay * len;
-    int partner = g.side_off[side] + (1 - lay) * len + t;
-    const cpx<T>* co = coefT + (size_t)op_of[s] * cstride;
-    cpx<T> cf;
-    if (side < 2) {
-      int q = side == 0 ? g.W : g.W + g.na[0];
-      cf = co[(size_t)t * (n + 1) + q];                   // ax[t][face]
-    } else {
-      int q = side == 2 ? g.W : g.W + g.na[1];
-      cf = co[(size_t)K * (n + 1) + (size_t)q * n + t];   // ay[face][t]
-    }
-    size_t base = ((size_t)s * C + col) * NI;
-    cpx<T> pv = slots[((size_t)L * g.nsub) * C * NI + base + partner];
-    cpx<T> gv = cf * pv;
-    if (lay == 0) gv = -gv;
-    gbuf[base + i] = gv;
-    accg[base + i] = accg[base + i] + gv;
-  }
-}
-template <class T>
-hipError_t launch_trace_source(hdsw_ctx* c, int L, int off, int cnt, int C) {
-  long long tot = (long long)cnt * C * c->g.NI;
-  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(k_trace_source<T>, dim3(blocks), dim3(256), 0, c->stream,
-                     (const cpx<T>*)c->d_slots, (cpx<T>*)c->d_g, (cpx<T>*)c->d_accg,
-                     (const cpx<T>*)c->d_coefT, c->coef_stride, c->d_op_of_sub,
-                     c->d_step_subs + off, cnt, L, C, c->gd);
-  return hipGetLastError();
-}
-
-// (interface GEMM: mfma.hip)
-
-// Route the traces of one step to the neighbours' slots (Algorithm 2.1:
-// add the transferred trace to the l'-th local trace of the neighbour).
-// The pair is the limit from the receiver's side: on a face that received a
-// pair in this sweep, the incoming value on the own layer is removed.
-struct LPrime { int v[6]; };
-template <class T>
-__global__ void k_route(cpx<T>* slots, const cpx<T>* out, const int* subs, int cnt,
-                        int L, LPrime lp, int C, GeoDev g) {
-  const int NI = g.NI;
-  const size_t slot_stride = (size_t)g.nsub * C * NI;
-  int maxlen = max(g.side_len[0], g.side_len[2]);
-  long long tot = (long long)cnt * 4 * C * maxlen;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int bi = (int)(idx / (4LL * C * maxlen));
-    int r = (int)(idx - (long long)bi * 4 * C * maxlen);
-    int f = r / (C * maxlen);
-    r -= f * C * maxlen;
-    int col = r / maxlen, t = r - col * maxlen;
-    int len = g.side_len[f];
-    if (t >= len) continue;
-    int lq = lp.v[f];
-    if (lq < 0) continue;
-    int s = subs[bi];
-    int sc[2] = {s % g.P[0], s / g.P[0]};
-    int axis = f >> 1, dir = (f & 1) ? 1 : -1;
-    sc[axis] += dir;
-    if (sc[axis] < 0 || sc[axis] >= g.P[axis]) continue;
-    int recv = sc[0] + g.P[0] * sc[1];
-    int fo = f ^ 1;
-    size_t sb = ((size_t)s * C + col) * NI;
-    size_t rb = (size_t)lq * slot_stride + ((size_t)recv * C + col) * NI;
-    cpx<T> o0 = out[sb + g.side_off[f] + t];
-    cpx<T> o1 = out[sb + g.side_off[f] + len + t];
-    cpx<T> in0 = slots[(size_t)L * slot_stride + sb + g.side_off[f] + t];
-    size_t r0 = rb + g.side_off[fo] + t, r1 = rb + g.side_off[fo] + len + t;
-    slots[r0] = slots[r0] + o1;
-    slots[r1] = slots[r1] + (o0 - in0);
-  }
-}
-template <class T>
-hipError_t launch_route(hdsw_ctx* c, int L, int off, int cnt, int C) {
-  LPrime lp;
-  for (int f = 0; f < 6; ++f) lp.v[f] = c->sch.lprime[L * 6 + f];
-  int maxlen = std::max(c->g.side_len[0], c->g.side_len[2]);
-  long long tot = (long long)cnt * 4 * C * maxlen;
-  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(k_route<T>, dim3(blocks), dim3(256), 0, c->stream,
-                     (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_out,
-                     c->d_step_subs + off, cnt, L, lp, C, c->gd);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------ FP64 global
 // b = h^2 J f on the global grid (J = 1 inside B, f = 0 in the layer)
 __global__ void k_rhs_from_f(const c128* f, c128* b, int C, GeoDev g, double h2,
@@ -608,9 +502,7 @@ hipError_t launch_scale(hdsw_ctx* c, c128* dst, const c128* src, const double* i
                                            const c128*, int);                        \
   template hipError_t launch_extract_iface<T>(hdsw_ctx*, int, int, void*, long long, \
                                               int);                                  \
-  template hipError_t launch_write_owned<T>(hdsw_ctx*, int, c128*, int);             \
-  template hipError_t launch_trace_source<T>(hdsw_ctx*, int, int, int, int);         \
-  template hipError_t launch_route<T>(hdsw_ctx*, int, int, int, int);
+  template hipError_t launch_write_owned<T>(hdsw_ctx*, int, c128*, int);
 HDSW_INST(float)
 HDSW_INST(double)
 

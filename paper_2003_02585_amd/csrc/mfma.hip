@@ -1,4 +1,4 @@
-// Factorization, batched block solve and interface GEMM of the hdsw library.
+// Factorization, batched block solve and fused sweep step of the hdsw library.
 //
 // Twisted ("from both ends") block-tridiagonal LU of a subdomain operator
 // with K grid lines and coupling B_k = diag(ay[k]) between lines k-1 and k,
@@ -48,77 +48,137 @@ struct MF<double> {
 };
 
 // ------------------------------------------------------------ matvec
-// yb[c][r] = sum_j Xb(r, j) vb[c][j] for 8 columns c (LDS vectors of length
-// nP, zero beyond n).  Waves split the rows in two halves of 16-row tiles
-// and the sum in KS = NW / 2 slices; the slices are added in a fixed order,
-// so results do not depend on timing.  Ends with the block synchronized.
-template <class T, int MAXT, int NW>
-__device__ inline void mfma_matvec(const cpx<T>* __restrict__ Xb, int nP, const cpx<T>* vb,
-                                   cpx<T>* yb, cpx<T>* red, int wave, int lane) {
-  typedef typename MF<T>::v4 v4;
-  constexpr int KS = NW / 2;
-  const int nMt = nP >> 4, nK = nP >> 2;
-  const int mh = wave & 1, kq = wave >> 1;
-  const int th = (nMt + 1) >> 1;
-  const int t0 = mh ? th : 0, nt = mh ? nMt - th : th;
-  const int kchunk = (nK + KS - 1) / KS;
-  const int k0 = kq * kchunk, k1 = min(nK, k0 + kchunk);
-  v4 acc[MAXT];
+// yb[r][c] = sum_j Xb(r, j) vb[j][c] for 8 columns c (LDS, row-major with the
+// 8 columns contiguous so one 4-row slice is 64 distinct banks; zero beyond
+// n).  Waves split the rows in two halves of 16-row tiles and the sum in
+// KS = NW / 2 slices; the slices are added in a fixed order, so results do
+// not depend on timing.
+//
+// A wave's X tiles are loaded in batches of KSB 4-deep slices; the first
+// batch of the next block is loaded while the current block is reduced and
+// its epilogue runs, so the load latency is hidden behind LDS work.
+template <class T, int MAXT, int KSB>
+struct WaveTiles {
+  cpx<T> x[KSB][MAXT];
+};
+
+template <class T, int MAXT, int KSB>
+__device__ __forceinline__ void mv_load(WaveTiles<T, MAXT, KSB>& w, const cpx<T>* __restrict__ Xb,
+                                        int nP, int t0, int nt, int kb0, int k1, int kk, int rr) {
+  const cpx<T>* base = Xb + (size_t)(t0 * 16 + rr);
 #pragma unroll
-  for (int t = 0; t < MAXT; ++t) acc[t] = v4{T(0), T(0), T(0), T(0)};
-  const int jc = lane & 15, cc = jc & 7, part = jc >> 3, kk = lane >> 4, rr = lane & 15;
-  const cpx<T>* xbase = Xb + (size_t)(t0 * 16 + rr);
-#pragma unroll 2
-  for (int ks = k0; ks < k1; ++ks) {
-    const int j = 4 * ks + kk;
-    const cpx<T> vv = vb[cc * nP + j];
-    const T b1 = part ? vv.im : vv.re;
-    const T b2 = part ? vv.re : -vv.im;
-    const cpx<T>* xc = xbase + (size_t)j * nP;
-    cpx<T> xa[MAXT];
+  for (int q = 0; q < KSB; ++q) {
+    const int ks = kb0 + q;
+    if (ks < k1) {
+      const cpx<T>* xc = base + (size_t)(4 * ks + kk) * nP;
 #pragma unroll
-    for (int t = 0; t < MAXT; ++t)
-      if (t < nt) xa[t] = xc[t * 16];
+      for (int t = 0; t < MAXT; ++t)
+        if (t < nt) w.x[q][t] = xc[t * 16];
+    }
+  }
+}
+
+template <class T, int MAXT, int KSB>
+__device__ __forceinline__ void mv_mfma(const WaveTiles<T, MAXT, KSB>& w,
+                                        typename MF<T>::v4 (&acc)[MAXT], const cpx<T>* vb,
+                                        int kb0, int k1, int nt, int kk, int cc, int part) {
 #pragma unroll
-    for (int t = 0; t < MAXT; ++t) {
-      if (t < nt) {
-        acc[t] = MF<T>::mfma(xa[t].re, b1, acc[t]);
-        acc[t] = MF<T>::mfma(xa[t].im, b2, acc[t]);
+  for (int q = 0; q < KSB; ++q) {
+    const int ks = kb0 + q;
+    if (ks < k1) {
+      const cpx<T> vv = vb[(4 * ks + kk) * 8 + cc];
+      const T b1 = part ? vv.im : vv.re;
+      const T b2 = part ? vv.re : -vv.im;
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        if (t < nt) {
+          acc[t] = MF<T>::mfma(w.x[q][t].re, b1, acc[t]);
+          acc[t] = MF<T>::mfma(w.x[q][t].im, b2, acc[t]);
+        }
       }
     }
   }
-  if (kq > 0) {
-    T* dst = reinterpret_cast<T*>(red + (size_t)(kq - 1) * 8 * nP);
+}
+
+// Wave geometry of the matvec
+struct WaveGeo {
+  int t0, nt, k0, k1, cc, part, kk, rr, kq;
+};
+template <int NW>
+__device__ inline WaveGeo wave_geo(int nP, int wave, int lane) {
+  constexpr int KS = NW / 2;
+  WaveGeo w;
+  const int nMt = nP >> 4, nK = nP >> 2;
+  const int mh = wave & 1;
+  w.kq = wave >> 1;
+  const int th = (nMt + 1) >> 1;
+  w.t0 = mh ? th : 0;
+  w.nt = mh ? nMt - th : th;
+  const int kchunk = (nK + KS - 1) / KS;
+  w.k0 = min(nK, w.kq * kchunk);
+  w.k1 = min(nK, w.k0 + kchunk);
+  const int jc = lane & 15;
+  w.cc = jc & 7;
+  w.part = jc >> 3;
+  w.kk = lane >> 4;
+  w.rr = lane & 15;
+  return w;
+}
+
+// One block product yb = X_k vc.  On entry `tiles` holds the first batch of
+// X_k; on exit it holds the first batch of Xnext (if not null).  Ends with
+// the block synchronized and yb complete.
+template <class T, int MAXT, int KSB, int NW>
+__device__ __forceinline__ void block_product(WaveTiles<T, MAXT, KSB>& tiles, const WaveGeo& wg,
+                                              const cpx<T>* __restrict__ Xk,
+                                              const cpx<T>* __restrict__ Xnext, int nP,
+                                              const cpx<T>* vc, cpx<T>* yb, cpx<T>* red,
+                                              int lane) {
+  typedef typename MF<T>::v4 v4;
+  constexpr int KS = NW / 2;
+  v4 acc[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) acc[t] = v4{T(0), T(0), T(0), T(0)};
+  mv_mfma<T, MAXT, KSB>(tiles, acc, vc, wg.k0, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
+  for (int kb = wg.k0 + KSB; kb < wg.k1; kb += KSB) {
+    mv_load<T, MAXT, KSB>(tiles, Xk, nP, wg.t0, wg.nt, kb, wg.k1, wg.kk, wg.rr);
+    mv_mfma<T, MAXT, KSB>(tiles, acc, vc, kb, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
+  }
+  if (Xnext) mv_load<T, MAXT, KSB>(tiles, Xnext, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk, wg.rr);
+  if (wg.kq > 0) {
+    T* dst = reinterpret_cast<T*>(red + (size_t)(wg.kq - 1) * 8 * nP);
 #pragma unroll
     for (int t = 0; t < MAXT; ++t)
-      if (t < nt)
+      if (t < wg.nt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          int row = 16 * (t0 + t) + MF<T>::row(lane, i);
-          dst[2 * (cc * nP + row) + part] = acc[t][i];
+          int row = 16 * (wg.t0 + t) + MF<T>::row(lane, i);
+          dst[2 * (row * 8 + wg.cc) + wg.part] = acc[t][i];
         }
   }
   __syncthreads();
-  if (kq == 0) {
+  if (wg.kq == 0) {
     T* y = reinterpret_cast<T*>(yb);
     const T* rd = reinterpret_cast<const T*>(red);
 #pragma unroll
     for (int t = 0; t < MAXT; ++t)
-      if (t < nt)
+      if (t < wg.nt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          int row = 16 * (t0 + t) + MF<T>::row(lane, i);
-          int idx = 2 * (cc * nP + row) + part;
-          T s = acc[t][i];
-          for (int q = 0; q < KS - 1; ++q) s += rd[(size_t)q * 16 * nP + idx];
-          y[idx] = s;
+          int row = 16 * (wg.t0 + t) + MF<T>::row(lane, i);
+          int idx = 2 * (row * 8 + wg.cc) + wg.part;
+          T sum = acc[t][i];
+          for (int q = 0; q < KS - 1; ++q) sum += rd[(size_t)q * 16 * nP + idx];
+          y[idx] = sum;
         }
   }
   __syncthreads();
 }
 
 // ------------------------------------------------------------ solve A
-template <class T, int MAXT, int NW>
+// EPT epilogue elements per thread have their global operands prefetched
+// before the block product (EPT * threads >= 8 n is checked at launch).
+template <class T, int MAXT, int KSB, int NW, int EPT>
 __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict__ X,
                                                        size_t xstride,
                                                        const cpx<T>* __restrict__ coefT,
@@ -140,29 +200,48 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
   cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
+  const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
   for (int idx = tid; idx < 16 * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
   __syncthreads();
   int k = half ? K - 1 : 0;
   const int nsteps = half ? K - 1 - mid : mid;
   for (int idx = tid; idx < 8 * n; idx += NT) {
     int c = idx / n, r = idx - c * n;
-    if (c < nc) vb0[c * nP + r] = pb[((size_t)k * C + c0 + c) * n + r];
+    if (c < nc) vb0[r * 8 + c] = pb[((size_t)k * C + c0 + c) * n + r];
   }
+  WaveTiles<T, MAXT, KSB> tiles;
+  mv_load<T, MAXT, KSB>(tiles, Xo + (size_t)k * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk,
+                        wg.rr);
   __syncthreads();
   cpx<T>* vc = vb0;
   cpx<T>* vn = vb1;
   for (int s = 0; s < nsteps; ++s) {
-    mfma_matvec<T, MAXT, NW>(Xo + (size_t)k * nP * nP, nP, vc, yb, red, wave, lane);
     const bool more = s + 1 < nsteps;
     const int kn = half ? k - 1 : k + 1;
     const int face = half ? k : k + 1;
-    for (int idx = tid; idx < 8 * n; idx += NT) {
+    // prefetch the epilogue operands: f of the next line and the coupling
+    cpx<T> fpre[EPT], apre[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (c < nc) {
-        cpx<T> y = yb[c * nP + r];
+      if (idx < 8 * n && c < nc) {
+        fpre[q] = pb[((size_t)kn * C + c0 + c) * n + r];
+        apre[q] = ay[(size_t)face * n + r];
+      }
+    }
+    block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
+                                    more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, yb, red,
+                                    lane);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      int idx = tid + q * NT;
+      int c = idx / n, r = idx - c * n;
+      if (idx < 8 * n && c < nc) {
+        cpx<T> y = yb[r * 8 + c];
         pb[((size_t)k * C + c0 + c) * n + r] = y;
-        cpx<T> nxt = pb[((size_t)kn * C + c0 + c) * n + r] - ay[(size_t)face * n + r] * y;
-        if (more) vn[c * nP + r] = nxt;
+        cpx<T> nxt = fpre[q] - apre[q] * y;
+        if (more) vn[r * 8 + c] = nxt;
         else if (half == 0)   // scratch line K: f_m - B_m w_{m-1}
           pb[((size_t)K * C + c0 + c) * n + r] = nxt;
       }
@@ -176,7 +255,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
 }
 
 // ------------------------------------------------------------ solve B
-template <class T, int MAXT, int NW>
+template <class T, int MAXT, int KSB, int NW, int EPT>
 __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict__ X,
                                                        size_t xstride,
                                                        const cpx<T>* __restrict__ coefT,
@@ -198,27 +277,44 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
   cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
+  const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
   for (int idx = tid; idx < 16 * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
   __syncthreads();
   // middle line: v = (f_m - B_m w_{m-1}) - B_{m+1} v_{m+1}
   for (int idx = tid; idx < 8 * n; idx += NT) {
     int c = idx / n, r = idx - c * n;
     if (c < nc)
-      vb0[c * nP + r] = pb[((size_t)K * C + c0 + c) * n + r] -
-                        ay[(size_t)(mid + 1) * n + r] * pb[((size_t)(mid + 1) * C + c0 + c) * n + r];
+      vb0[r * 8 + c] = pb[((size_t)K * C + c0 + c) * n + r] -
+                       ay[(size_t)(mid + 1) * n + r] * pb[((size_t)(mid + 1) * C + c0 + c) * n + r];
   }
+  WaveTiles<T, MAXT, KSB> tiles;
+  mv_load<T, MAXT, KSB>(tiles, Xo + (size_t)mid * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1,
+                        wg.kk, wg.rr);
   __syncthreads();
   cpx<T>* vc = vb0;
   cpx<T>* vn = vb1;
-  mfma_matvec<T, MAXT, NW>(Xo + (size_t)mid * nP * nP, nP, vc, yb, red, wave, lane);
+  const int nsteps = half ? K - 1 - mid : mid;
+  int k = half ? mid + 1 : mid - 1;
   {
     const int face = half ? mid + 1 : mid;
-    for (int idx = tid; idx < 8 * n; idx += NT) {
+    cpx<T> apre[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (c < nc) {
-        cpx<T> x = yb[c * nP + r];
+      if (idx < 8 * n && c < nc) apre[q] = ay[(size_t)face * n + r];
+    }
+    block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)mid * nP * nP,
+                                    nsteps > 0 ? Xo + (size_t)k * nP * nP : nullptr, nP, vc,
+                                    yb, red, lane);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      int idx = tid + q * NT;
+      int c = idx / n, r = idx - c * n;
+      if (idx < 8 * n && c < nc) {
+        cpx<T> x = yb[r * 8 + c];
         if (half == 0) pb[((size_t)mid * C + c0 + c) * n + r] = x;
-        vn[c * nP + r] = ay[(size_t)face * n + r] * x;
+        vn[r * 8 + c] = apre[q] * x;
       }
     }
     __syncthreads();
@@ -226,23 +322,35 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     vc = vn;
     vn = t;
   }
-  int k = half ? mid + 1 : mid - 1;
-  const int nsteps = half ? K - 1 - mid : mid;
   for (int s = 0; s < nsteps; ++s) {
-    mfma_matvec<T, MAXT, NW>(Xo + (size_t)k * nP * nP, nP, vc, yb, red, wave, lane);
     const bool more = s + 1 < nsteps;
+    const int kn = half ? k + 1 : k - 1;
     const int face = half ? k + 1 : k;
-    for (int idx = tid; idx < 8 * n; idx += NT) {
+    cpx<T> wpre[EPT], apre[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (c < nc) {
-        size_t o = ((size_t)k * C + c0 + c) * n + r;
-        cpx<T> x = pb[o] - yb[c * nP + r];
-        pb[o] = x;
-        if (more) vn[c * nP + r] = ay[(size_t)face * n + r] * x;
+      if (idx < 8 * n && c < nc) {
+        wpre[q] = pb[((size_t)k * C + c0 + c) * n + r];
+        apre[q] = ay[(size_t)face * n + r];
+      }
+    }
+    block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
+                                    more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, yb, red,
+                                    lane);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      int idx = tid + q * NT;
+      int c = idx / n, r = idx - c * n;
+      if (idx < 8 * n && c < nc) {
+        cpx<T> x = wpre[q] - yb[r * 8 + c];
+        pb[((size_t)k * C + c0 + c) * n + r] = x;
+        if (more) vn[r * 8 + c] = apre[q] * x;
       }
     }
     __syncthreads();
-    k += half ? 1 : -1;
+    k = kn;
     cpx<T>* t = vc;
     vc = vn;
     vn = t;
@@ -251,43 +359,54 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
 
 template <class T>
 static int solve_nw(int nP) {
-  // 8 waves (sum split in 4 slices) when the LDS fits, else 4 waves
+  // as many waves as the LDS allows: (2 + NW/2) vectors of 8 x nP complex
   size_t e = sizeof(cpx<T>);
-  return (6 * 8 * (size_t)nP * e <= 160 * 1024) ? 8 : 4;
+  auto fits = [&](int nw) { return (size_t)(2 + nw / 2) * 8 * nP * e <= 160 * 1024; };
+  if (fits(8)) return 8;
+  if (fits(4)) return 4;
+  return 0;
 }
+
+// 4-deep slices loaded per batch: as many as fit in registers without spills
+template <class T>
+struct SolveKSB { static constexpr int v = sizeof(T) == 4 ? 5 : 3; };
 
 template <class T, int MAXT, int NW>
 static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
+  constexpr int EPT = 2048 / (NW * 64);
   const Geometry& g = c->g;
+  if (8 * g.n > EPT * NW * 64) return hipErrorInvalidValue;
   dim3 grid((C + 7) / 8, nbatch, 2);
   size_t lds = (size_t)(2 + NW / 2) * 8 * g.nP * sizeof(cpx<T>);
   size_t xstride = (size_t)g.K * g.nP * g.nP;
-  hipLaunchKernelGGL((k_solve_fwd<T, MAXT, NW>), grid, dim3(NW * 64), lds, c->stream,
-                     (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
+  hipLaunchKernelGGL((k_solve_fwd<T, MAXT, SolveKSB<T>::v, NW, EPT>), grid, dim3(NW * 64), lds,
+                     c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
                      c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve_bwd<T, MAXT, NW>), grid, dim3(NW * 64), lds, c->stream,
-                     (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
+  hipLaunchKernelGGL((k_solve_bwd<T, MAXT, SolveKSB<T>::v, NW, EPT>), grid, dim3(NW * 64), lds,
+                     c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
                      c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
   return hipGetLastError();
 }
 
+template <class T, int NW>
+static hipError_t launch_solve_nw(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
+  const int nMt = c->g.nP / 16;
+  const int th = (nMt + 1) / 2;
+  if (th <= 2) return launch_solve_t<T, 2, NW>(c, nbatch, d_ops, C);
+  if (th <= 3) return launch_solve_t<T, 3, NW>(c, nbatch, d_ops, C);
+  if (th <= 5) return launch_solve_t<T, 5, NW>(c, nbatch, d_ops, C);
+  if (th <= 8) return launch_solve_t<T, 8, NW>(c, nbatch, d_ops, C);
+  if (th <= 16) return launch_solve_t<T, 16, NW>(c, nbatch, d_ops, C);
+  return hipErrorInvalidValue;
+}
+
 template <class T>
 hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
-  const int nMt = c->g.nP / 16;
-  const int half = (nMt + 1) / 2;
   const int nw = solve_nw<T>(c->g.nP);
-  if ((size_t)(2 + nw / 2) * 8 * c->g.nP * sizeof(cpx<T>) > 160 * 1024) return hipErrorInvalidValue;
-  if (half <= 4)
-    return nw == 8 ? launch_solve_t<T, 4, 8>(c, nbatch, d_ops, C)
-                   : launch_solve_t<T, 4, 4>(c, nbatch, d_ops, C);
-  if (half <= 8)
-    return nw == 8 ? launch_solve_t<T, 8, 8>(c, nbatch, d_ops, C)
-                   : launch_solve_t<T, 8, 4>(c, nbatch, d_ops, C);
-  if (half <= 16)
-    return nw == 8 ? launch_solve_t<T, 16, 8>(c, nbatch, d_ops, C)
-                   : launch_solve_t<T, 16, 4>(c, nbatch, d_ops, C);
+  if (nw == 8) return launch_solve_nw<T, 8>(c, nbatch, d_ops, C);
+  if (nw == 4) return launch_solve_nw<T, 4>(c, nbatch, d_ops, C);
   return hipErrorInvalidValue;
 }
 
@@ -444,90 +563,321 @@ hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ interface GEMM
-// out[s][col][:] = T_op(s) g[s][col][:] (+ y[s][col][:]): the subdomain
-// solve of one sweep step restricted to its interface layers.  One
-// workgroup per (64 output rows, 8 columns, subdomain); each wave owns one
-// 16-row tile over the whole sum; the step's sources are staged in LDS.
+// ------------------------------------------------------------ sweep step
+// One step of a sweep for the subdomains of one anti-diagonal, fused:
+//   1. trace -> source: g = [S_r, chi_r] v~ from the pairs in the step's
+//      sweep slot (g[layer 1] = c pair[layer 0], g[layer 0] = -c pair[layer 1],
+//      c = the face coefficient of the receiver); the first row tile also
+//      accumulates g for the final owned-node solve;
+//   2. the subdomain solve restricted to the interface layers,
+//      out = T g (+ y in the sweep that carries the sources f_ij);
+//   3. routing: each output pair goes into slot l' of the neighbour across
+//      its face, taken as the limit from the receiver's side (the layer on
+//      the sender's side loses the pair the sender received there).
+// Only faces that can hold a trace in this sweep enter the sum, and only
+// faces whose traces have a destination are computed.  One workgroup per
+// (64 output rows, 16 columns, subdomain); a wave owns one 16-row tile and
+// two 8-column MFMA tiles over the whole sum.
+struct FaceSet {
+  int n;                 // active faces
+  int face[4];           // face ids (0:-x, 1:+x, 2:-y, 3:+y)
+  int start[4];          // first row (or sum index) of the face
+  int lq[4];             // destination sweep per face (outputs only)
+};
+__device__ inline int fs_find(const FaceSet& fs, int idx) {
+  int q = 0;
+  while (q + 1 < fs.n && idx >= fs.start[q + 1]) ++q;
+  return q;
+}
+
+// Trace -> source for every subdomain of the step, once:
+//   g[layer 1] = c pair[layer 0],  g[layer 0] = -c pair[layer 1],
+// written in the GEMM's operand layout gbuf[s][ct][k][8] (k over the active
+// input faces, 8-column tiles, zero-padded columns) and added to the
+// sources accumulated for the final owned-node solve.
 template <class T>
-__global__ __launch_bounds__(256) void k_iface_gemm(const cpx<T>* __restrict__ Tm,
-                                                    const cpx<T>* __restrict__ gbuf,
-                                                    const cpx<T>* __restrict__ ybuf,
-                                                    cpx<T>* __restrict__ out,
-                                                    const int* __restrict__ op_of,
-                                                    const int* __restrict__ subs, int C, int NI,
-                                                    int NIc, int add_y) {
-  typedef typename MF<T>::v4 v4;
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* gs = reinterpret_cast<cpx<T>*>(smem_raw);   // [8][NIc]; reused for output
-  const int s = subs[blockIdx.z];
-  const int c0 = blockIdx.y * 8, nc = min(8, C - c0);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int row0 = blockIdx.x * 64 + wave * 16;
-  const cpx<T>* Top = Tm + (size_t)op_of[s] * NI * NI;
-  const cpx<T>* gb = gbuf + ((size_t)s * C + c0) * NI;
-  const int jc = lane & 15, cc = jc & 7, part = jc >> 3, kk = lane >> 4, rr = lane & 15;
-  const int myrow = row0 + rr;
-  v4 acc = v4{T(0), T(0), T(0), T(0)};
-  for (int jb = 0; jb < NI; jb += NIc) {
-    const int jn = min(NIc, NI - jb);
-    __syncthreads();
-    for (int idx = tid; idx < 8 * NIc; idx += 256) {
-      int cq = idx / NIc, j = idx - cq * NIc;
-      gs[idx] = (cq < nc && j < jn) ? gb[(size_t)cq * NI + jb + j] : mk<T>(T(0), T(0));
+__global__ void k_trace_src(const cpx<T>* __restrict__ cface, const cpx<T>* __restrict__ slots,
+                            cpx<T>* gbuf, cpx<T>* accg, const int* __restrict__ op_of,
+                            const int* __restrict__ subs, int cnt, int L, int C, int Cp,
+                            FaceSet fin, int nin, GeoDev g) {
+  const int NI = g.NI;
+  const size_t slot_stride = (size_t)g.nsub * C * NI;
+  long long tot = (long long)cnt * Cp * nin;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int bi = (int)(idx / ((long long)Cp * nin));
+    int r = (int)(idx - (long long)bi * Cp * nin);
+    int ct = r / (nin * 8);
+    int r2 = r - ct * nin * 8;
+    int k = r2 >> 3, cl = r2 & 7;
+    int col = ct * 8 + cl;
+    int s = subs[bi];
+    cpx<T> gv = mk<T>(T(0), T(0));
+    if (col < C) {
+      int q = fs_find(fin, k);
+      int f = fin.face[q];
+      int len = g.side_len[f];
+      int rq = k - fin.start[q];
+      int lay = rq / len, t = rq - lay * len;
+      int d = g.side_off[f] + rq;
+      int partner = g.side_off[f] + (1 - lay) * len + t;
+      const cpx<T>* sl = slots + (size_t)L * slot_stride + ((size_t)s * C + col) * NI;
+      gv = cface[(size_t)op_of[s] * (NI / 2) + g.side_off[f] / 2 + t] * sl[partner];
+      if (lay == 0) gv = -gv;
+      size_t o = ((size_t)s * C + col) * NI + d;
+      accg[o] = accg[o] + gv;
     }
-    __syncthreads();
-    const cpx<T>* xc = Top + (size_t)jb * NI + myrow;
-    const bool rowok = myrow < NI;
-#pragma unroll 4
-    for (int ks = 0; ks < (jn >> 2); ++ks) {
-      const int j = 4 * ks + kk;
-      const cpx<T> vv = gs[cc * NIc + j];
-      const T b1 = part ? vv.im : vv.re;
-      const T b2 = part ? vv.re : -vv.im;
-      cpx<T> xa = rowok ? xc[(size_t)j * NI] : mk<T>(T(0), T(0));
-      acc = MF<T>::mfma(xa.re, b1, acc);
-      acc = MF<T>::mfma(xa.im, b2, acc);
-    }
-  }
-  __syncthreads();
-  // stage the 64 x 8 output tile in LDS, then write rows coalesced
-  T* st = reinterpret_cast<T*>(gs);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int row = wave * 16 + MF<T>::row(lane, i);
-    st[2 * (cc * 64 + row) + part] = acc[i];
-  }
-  __syncthreads();
-  for (int idx = tid; idx < 8 * 64; idx += 256) {
-    int cq = idx / 64, r = idx - cq * 64;
-    int row = blockIdx.x * 64 + r;
-    if (cq < nc && row < NI) {
-      size_t o = ((size_t)s * C + c0 + cq) * NI + row;
-      cpx<T> v = gs[cq * 64 + r];
-      if (add_y) v = v + ybuf[o];
-      out[o] = v;
-    }
+    gbuf[(size_t)s * Cp * NI + ((size_t)ct * nin + k) * 8 + cl] = gv;
   }
 }
 
+// Epilogue of the sweep step for one output element: where its value goes.
+struct StepOut {
+  long long dst;     // slot element to add to (-1: none)
+  long long yo;      // y element (source-driven part), -1 if not added
+  long long ino;     // incoming pair element to subtract, -1 if none
+};
+__device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, int orow,
+                                   int col, int C, int L, size_t slot_stride, int add_y) {
+  StepOut o{-1, -1, -1};
+  const int NI = g.NI;
+  int q = fs_find(fout, orow);
+  int f = fout.face[q];
+  int lq = fout.lq[q];
+  int len = g.side_len[f];
+  int rq = orow - fout.start[q];
+  int lay = rq / len, t = rq - lay * len;
+  int d = g.side_off[f] + rq;
+  int scc[2] = {s % g.P[0], s / g.P[0]};
+  int axis = f >> 1;
+  scc[axis] += (f & 1) ? 1 : -1;
+  if (scc[axis] < 0 || scc[axis] >= g.P[axis]) return o;
+  int recv = scc[0] + g.P[0] * scc[1];
+  int fo = f ^ 1;
+  size_t rb = (size_t)lq * slot_stride + ((size_t)recv * C + col) * NI;
+  if (add_y) o.yo = (long long)(((size_t)s * C + col) * NI + d);
+  if (lay == 1) {
+    o.dst = (long long)(rb + g.side_off[fo] + t);
+  } else {
+    o.dst = (long long)(rb + g.side_off[fo] + len + t);
+    o.ino = (long long)((size_t)L * slot_stride + ((size_t)s * C + col) * NI + g.side_off[f] + t);
+  }
+  return o;
+}
+
+template <class T, int KB, int KC>
+__global__ __launch_bounds__(256) void k_sweep_step(
+    const cpx<T>* __restrict__ Tm, const cpx<T>* __restrict__ gbuf, cpx<T>* slots,
+    const cpx<T>* __restrict__ ybuf, const int* __restrict__ op_of,
+    const int* __restrict__ subs, int L, int C, int Cp, FaceSet fin, int nin, FaceSet fout,
+    int nout, int add_y, GeoDev g) {
+  typedef typename MF<T>::v4 v4;
+  typedef typename MF<T>::v4 copy_t;       // 16 bytes (f32) / 32 bytes (f64)
+  constexpr int CPX_PER_COPY = sizeof(copy_t) / sizeof(cpx<T>);
+  constexpr int COPIES = 2 * KC * 8 / CPX_PER_COPY / 256;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* gs = reinterpret_cast<cpx<T>*>(smem_raw);        // [2][KC][8]
+  int* kdof = reinterpret_cast<int*>(gs + 2 * KC * 8);     // [KC]
+  const int NI = g.NI;
+  const int s = subs[blockIdx.z];
+  const int cg = blockIdx.y;                               // 16-column group
+  const int c0 = cg * 16;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int op = op_of[s];
+  const cpx<T>* Top = Tm + (size_t)op * NI * NI;
+  const size_t slot_stride = (size_t)g.nsub * C * NI;
+  const cpx<T>* gsrc = gbuf + (size_t)s * Cp * NI;
+  const int jc = lane & 15, cc = jc & 7, part = jc >> 3, kk = lane >> 4, rr = lane & 15;
+  const cpx<T> z = mk<T>(T(0), T(0));
+  // epilogue operands do not depend on the product: fetch them first
+  StepOut eo[4];
+  cpx<T> ey[4], ein[4], edst[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int idx = tid + q * 256;
+    int col = idx >> 6, r = idx & 63;
+    int orow = blockIdx.x * 64 + r;
+    eo[q] = StepOut{-1, -1, -1};
+    if (orow < nout && c0 + col < C)
+      eo[q] = step_out(g, fout, s, orow, c0 + col, C, L, slot_stride, add_y);
+    ey[q] = eo[q].yo >= 0 ? ybuf[eo[q].yo] : z;
+    ein[q] = eo[q].ino >= 0 ? slots[eo[q].ino] : z;
+    edst[q] = eo[q].dst >= 0 ? slots[eo[q].dst] : z;
+  }
+  // output dof of this lane's A row
+  const int row = blockIdx.x * 64 + wave * 16 + rr;
+  int dout = -1;
+  if (row < nout) {
+    int q = fs_find(fout, row);
+    dout = g.side_off[fout.face[q]] + (row - fout.start[q]);
+  }
+  const cpx<T>* Arow = Top + (dout >= 0 ? dout : 0);
+  v4 acc0 = v4{T(0), T(0), T(0), T(0)}, acc1 = acc0;
+  for (int kb = 0; kb < nin; kb += KC) {
+    const int kn = min(KC, nin - kb);
+    __syncthreads();
+    // copy the two 8-column tiles of this chunk (contiguous in gbuf), all
+    // loads issued before the stores
+    {
+      copy_t buf[COPIES];
+      const copy_t* src0 = reinterpret_cast<const copy_t*>(gsrc + ((size_t)(2 * cg) * nin + kb) * 8);
+      const copy_t* src1 = reinterpret_cast<const copy_t*>(gsrc + ((size_t)(2 * cg + 1) * nin + kb) * 8);
+      constexpr int PER_TILE = KC * 8 / CPX_PER_COPY;
+#pragma unroll
+      for (int u = 0; u < COPIES; ++u) {
+        int idx = tid + u * 256;
+        int t = idx / PER_TILE, r = idx - t * PER_TILE;
+        int k = r * CPX_PER_COPY / 8;
+        buf[u] = k < kn ? (t ? src1[r] : src0[r]) : copy_t{T(0), T(0), T(0), T(0)};
+      }
+      copy_t* dst = reinterpret_cast<copy_t*>(gs);
+#pragma unroll
+      for (int u = 0; u < COPIES; ++u) dst[tid + u * 256] = buf[u];
+    }
+    for (int k = tid; k < KC; k += 256) {
+      int d = -1;
+      if (k < kn) {
+        int q = fs_find(fin, kb + k);
+        d = g.side_off[fin.face[q]] + (kb + k - fin.start[q]);
+      }
+      kdof[k] = d;
+    }
+    __syncthreads();
+    const int nks = kn >> 2;
+    // T operand: batches of KB 4-deep slices, the next batch in flight while
+    // the current one feeds the matrix cores
+    cpx<T> a0[KB], a1[KB];
+    auto load = [&](cpx<T>(&a)[KB], int ks0) {
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        int ks = ks0 + u;
+        a[u] = (ks < nks && dout >= 0) ? Arow[(size_t)kdof[4 * ks + kk] * NI] : z;
+      }
+    };
+    auto compute = [&](const cpx<T>(&a)[KB], int ks0) {
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        int ks = ks0 + u;
+        if (ks < nks) {
+          const int k = 4 * ks + kk;
+          const cpx<T> v0 = gs[k * 8 + cc];
+          const cpx<T> v1 = gs[(KC + k) * 8 + cc];
+          acc0 = MF<T>::mfma(a[u].re, part ? v0.im : v0.re, acc0);
+          acc0 = MF<T>::mfma(a[u].im, part ? v0.re : -v0.im, acc0);
+          acc1 = MF<T>::mfma(a[u].re, part ? v1.im : v1.re, acc1);
+          acc1 = MF<T>::mfma(a[u].im, part ? v1.re : -v1.im, acc1);
+        }
+      }
+    };
+    load(a0, 0);
+    for (int ks0 = 0; ks0 < nks; ks0 += 2 * KB) {
+      load(a1, ks0 + KB);
+      compute(a0, ks0);
+      load(a0, ks0 + 2 * KB);
+      compute(a1, ks0 + KB);
+    }
+  }
+  __syncthreads();
+  // stage the 64 x 16 tile: st[col][row] complex
+  T* st = reinterpret_cast<T*>(gs);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int r = wave * 16 + MF<T>::row(lane, i);
+    st[2 * (cc * 64 + r) + part] = acc0[i];
+    st[2 * ((cc + 8) * 64 + r) + part] = acc1[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (eo[q].dst < 0) continue;
+    int idx = tid + q * 256;
+    int col = idx >> 6, r = idx & 63;
+    cpx<T> v = gs[col * 64 + r] + ey[q];
+    slots[eo[q].dst] = edst[q] + (v - ein[q]);
+  }
+}
+
+// face coefficients c(face, t) of every distinct operator, contiguous per
+// face: [op][side_off[f] / 2 + t]
 template <class T>
-hipError_t launch_iface_gemm(hdsw_ctx* c, int off, int cnt, int C, int add_y) {
-  int NI = c->g.NI;
-  int NIc = sizeof(T) == 4 ? 1024 : 512;
-  NIc = std::min(NIc, (NI + 3) / 4 * 4);
-  dim3 grid((NI + 63) / 64, (C + 7) / 8, cnt);
-  size_t lds = std::max<size_t>((size_t)8 * NIc, 8 * 64) * sizeof(cpx<T>);
-  hipLaunchKernelGGL(k_iface_gemm<T>, grid, dim3(256), lds, c->stream, (const cpx<T>*)c->d_T,
-                     (const cpx<T>*)c->d_g, (const cpx<T>*)c->d_y, (cpx<T>*)c->d_out,
-                     c->d_op_of_sub, c->d_step_subs + off, C, NI, NIc, add_y);
+__global__ void k_face_coef(cpx<T>* cface, const cpx<T>* coefT, size_t cstride, GeoDev g,
+                            int nops) {
+  const int half = g.NI / 2;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nops * half;
+       idx += gridDim.x * blockDim.x) {
+    int op = idx / half, i = idx - op * half;
+    int f = 0;
+    while (f < 3 && i >= g.side_off[f + 1] / 2) ++f;
+    int t = i - g.side_off[f] / 2;
+    const cpx<T>* co = coefT + (size_t)op * cstride;
+    cpx<T> v;
+    if (f < 2) v = co[(size_t)t * (g.n + 1) + (f == 0 ? g.W : g.W + g.na[0])];
+    else v = co[(size_t)g.K * (g.n + 1) + (size_t)(f == 2 ? g.W : g.W + g.na[1]) * g.n + t];
+    cface[idx] = v;
+  }
+}
+template <class T>
+hipError_t launch_face_coef(hdsw_ctx* c) {
+  int tot = c->nops * c->g.NI / 2;
+  hipLaunchKernelGGL(k_face_coef<T>, dim3((tot + 255) / 256), dim3(256), 0, c->stream,
+                     (cpx<T>*)c->d_cface, (const cpx<T>*)c->d_coefT, c->coef_stride, c->gd,
+                     c->nops);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C) {
+  const Geometry& g = c->g;
+  FaceSet fin{}, fout{};
+  int nin = 0, nout = 0;
+  for (int f = 0; f < 2 * g.dim; ++f) {
+    if (c->sch.in_active[L * 6 + f]) {
+      fin.face[fin.n] = f;
+      fin.start[fin.n] = nin;
+      fin.lq[fin.n] = -1;
+      fin.n++;
+      nin += 2 * g.side_len[f];
+    }
+    int lq = c->sch.lprime[L * 6 + f];
+    if (lq >= 0) {
+      fout.face[fout.n] = f;
+      fout.start[fout.n] = nout;
+      fout.lq[fout.n] = lq;
+      fout.n++;
+      nout += 2 * g.side_len[f];
+    }
+  }
+  if (nout == 0) return hipSuccess;
+  if (fin.n == 0) { fin.n = 1; fin.face[0] = 0; fin.start[0] = 0; }
+  const int Cp = (C + 15) / 16 * 16;
+  {
+    long long tot = (long long)cnt * Cp * nin;
+    int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+    if (tot > 0)
+      hipLaunchKernelGGL(k_trace_src<T>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const cpx<T>*)c->d_cface, (const cpx<T>*)c->d_slots,
+                         (cpx<T>*)c->d_g, (cpx<T>*)c->d_accg, c->d_op_of_sub,
+                         c->d_step_subs + off, cnt, L, C, Cp, fin, nin, c->gd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // KC: input dofs per LDS chunk (2 tiles x KC x 8 complex = 64 KB)
+  constexpr int KC = sizeof(T) == 4 ? 512 : 256;
+  constexpr int KB = sizeof(T) == 4 ? 16 : 6;
+  dim3 grid((nout + 63) / 64, Cp / 16, cnt);
+  size_t lds = (size_t)2 * KC * 8 * sizeof(cpx<T>) + (size_t)KC * sizeof(int);
+  hipLaunchKernelGGL((k_sweep_step<T, KB, KC>), grid, dim3(256), lds, c->stream,
+                     (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_g, (cpx<T>*)c->d_slots,
+                     (const cpx<T>*)c->d_y, c->d_op_of_sub, c->d_step_subs + off, L, C, Cp,
+                     fin, nin, fout, nout, L == 0 ? 1 : 0, c->gd);
   return hipGetLastError();
 }
 
 #define HDSW_INST2(T)                                                          \
   template hipError_t launch_block_solve<T>(hdsw_ctx*, int, const int*, int);  \
   template hipError_t launch_factor_step<T>(hdsw_ctx*, int, int);              \
-  template hipError_t launch_iface_gemm<T>(hdsw_ctx*, int, int, int, int);
+  template hipError_t launch_sweep_step<T>(hdsw_ctx*, int, int, int, int);     \
+  template hipError_t launch_face_coef<T>(hdsw_ctx*);
 HDSW_INST2(float)
 HDSW_INST2(double)
 
