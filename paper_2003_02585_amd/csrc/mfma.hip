@@ -665,38 +665,50 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
   return o;
 }
 
-template <class T, int KB, int KC>
-__global__ __launch_bounds__(256) void k_sweep_step(
+// The sum runs face by face over the active input faces.  For each face the
+// B operand is staged in LDS already split for the two real MFMAs of the
+// complex product: for column c < 8 of a tile, lane column jc = c carries
+// (Re v, -Im v) and jc = c + 8 carries (Im v, Re v), so every lane reads one
+// pair per 4-deep slice.  Four accumulators (two tiles x real/imaginary part
+// of X) keep dependent MFMAs apart; the T columns of a face are contiguous,
+// so its operand is walked by pointer increments.
+template <class T, int KB>
+__global__ __launch_bounds__(512) void k_sweep_step(
     const cpx<T>* __restrict__ Tm, const cpx<T>* __restrict__ gbuf, cpx<T>* slots,
     const cpx<T>* __restrict__ ybuf, const int* __restrict__ op_of,
     const int* __restrict__ subs, int L, int C, int Cp, FaceSet fin, int nin, FaceSet fout,
-    int nout, int add_y, GeoDev g) {
+    int nout, int add_y, int LMAX, int nsub_chunks, GeoDev g) {
   typedef typename MF<T>::v4 v4;
-  typedef typename MF<T>::v4 copy_t;       // 16 bytes (f32) / 32 bytes (f64)
-  constexpr int CPX_PER_COPY = sizeof(copy_t) / sizeof(cpx<T>);
-  constexpr int COPIES = 2 * KC * 8 / CPX_PER_COPY / 256;
   extern __shared__ unsigned char smem_raw[];
-  cpx<T>* gs = reinterpret_cast<cpx<T>*>(smem_raw);        // [2][KC][8]
-  int* kdof = reinterpret_cast<int*>(gs + 2 * KC * 8);     // [KC]
+  cpx<T>* bp = reinterpret_cast<cpx<T>*>(smem_raw);        // [2 tiles][LMAX][16] pairs
   const int NI = g.NI;
-  const int s = subs[blockIdx.z];
+  // XCD-aware mapping: workgroups are dispatched round-robin over the 8
+  // XCDs, so ids with the same id % 8 share an L2.  All subdomains of one
+  // row tile get the same XCD, so its slice of T is fetched into that L2.
+  const int nrt = (nout + 63) / 64;
+  const int cnt = gridDim.x / (8 * ((nrt + 7) / 8));
+  const int xcd = blockIdx.x & 7, q8 = blockIdx.x >> 3;
+  const int rtile = xcd + 8 * (q8 / cnt);
+  if (rtile >= nrt) return;
+  const int s = subs[q8 % cnt];
   const int cg = blockIdx.y;                               // 16-column group
   const int c0 = cg * 16;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rw = wave & 3, kh = wave >> 2;                 // row tile, half of the sum
   const int op = op_of[s];
   const cpx<T>* Top = Tm + (size_t)op * NI * NI;
   const size_t slot_stride = (size_t)g.nsub * C * NI;
   const cpx<T>* gsrc = gbuf + (size_t)s * Cp * NI;
-  const int jc = lane & 15, cc = jc & 7, part = jc >> 3, kk = lane >> 4, rr = lane & 15;
+  const int jc = lane & 15, kk = lane >> 4, rr = lane & 15;
   const cpx<T> z = mk<T>(T(0), T(0));
   // epilogue operands do not depend on the product: fetch them first
-  StepOut eo[4];
-  cpx<T> ey[4], ein[4], edst[4];
+  StepOut eo[2];
+  cpx<T> ey[2], ein[2], edst[2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int idx = tid + q * 256;
+  for (int q = 0; q < 2; ++q) {
+    int idx = tid + q * 512;
     int col = idx >> 6, r = idx & 63;
-    int orow = blockIdx.x * 64 + r;
+    int orow = rtile * 64 + r;
     eo[q] = StepOut{-1, -1, -1};
     if (orow < nout && c0 + col < C)
       eo[q] = step_out(g, fout, s, orow, c0 + col, C, L, slot_stride, add_y);
@@ -705,94 +717,113 @@ __global__ __launch_bounds__(256) void k_sweep_step(
     edst[q] = eo[q].dst >= 0 ? slots[eo[q].dst] : z;
   }
   // output dof of this lane's A row
-  const int row = blockIdx.x * 64 + wave * 16 + rr;
+  const int row = rtile * 64 + rw * 16 + rr;
   int dout = -1;
   if (row < nout) {
     int q = fs_find(fout, row);
     dout = g.side_off[fout.face[q]] + (row - fout.start[q]);
   }
-  const cpx<T>* Arow = Top + (dout >= 0 ? dout : 0);
-  v4 acc0 = v4{T(0), T(0), T(0), T(0)}, acc1 = acc0;
-  for (int kb = 0; kb < nin; kb += KC) {
-    const int kn = min(KC, nin - kb);
+  v4 aR0 = v4{T(0), T(0), T(0), T(0)}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+  for (int qc = 0; qc < fin.n * nsub_chunks; ++qc) {
+    const int qf = qc / nsub_chunks, sc = qc - qf * nsub_chunks;
+    const int f = fin.face[qf];
+    const int flen = 2 * g.side_len[f];
+    const int kb = sc * LMAX;                  // chunk of this face's sum
+    if (kb >= flen) continue;
+    const int kn = min(LMAX, flen - kb);       // sum length of this chunk
+    const int kst = fin.start[qf] + kb;        // its offset in the staged sources
+    const int nks = (kn + 3) >> 2;             // 4-deep slices, last one padded
     __syncthreads();
-    // copy the two 8-column tiles of this chunk (contiguous in gbuf), all
-    // loads issued before the stores
-    {
-      copy_t buf[COPIES];
-      const copy_t* src0 = reinterpret_cast<const copy_t*>(gsrc + ((size_t)(2 * cg) * nin + kb) * 8);
-      const copy_t* src1 = reinterpret_cast<const copy_t*>(gsrc + ((size_t)(2 * cg + 1) * nin + kb) * 8);
-      constexpr int PER_TILE = KC * 8 / CPX_PER_COPY;
-#pragma unroll
-      for (int u = 0; u < COPIES; ++u) {
-        int idx = tid + u * 256;
-        int t = idx / PER_TILE, r = idx - t * PER_TILE;
-        int k = r * CPX_PER_COPY / 8;
-        buf[u] = k < kn ? (t ? src1[r] : src0[r]) : copy_t{T(0), T(0), T(0), T(0)};
-      }
-      copy_t* dst = reinterpret_cast<copy_t*>(gs);
-#pragma unroll
-      for (int u = 0; u < COPIES; ++u) dst[tid + u * 256] = buf[u];
-    }
-    for (int k = tid; k < KC; k += 256) {
-      int d = -1;
-      if (k < kn) {
-        int q = fs_find(fin, kb + k);
-        d = g.side_off[fin.face[q]] + (kb + k - fin.start[q]);
-      }
-      kdof[k] = d;
+    for (int idx = tid; idx < 2 * (4 * nks) * 8; idx += 512) {
+      int t = idx / (4 * nks * 8), r = idx - t * 4 * nks * 8;
+      int k = r >> 3, c = r & 7;
+      cpx<T> v = k < kn ? gsrc[((size_t)(2 * cg + t) * nin + kst + k) * 8 + c] : z;
+      cpx<T>* row16 = bp + ((size_t)t * LMAX + k) * 16;
+      row16[c] = mk<T>(v.re, -v.im);
+      row16[c + 8] = mk<T>(v.im, v.re);
     }
     __syncthreads();
-    const int nks = kn >> 2;
-    // T operand: batches of KB 4-deep slices, the next batch in flight while
-    // the current one feeds the matrix cores
+    // this wave's half of the slices
+    const int hh = (nks + 1) >> 1;
+    const int ksb = kh * hh, kse = min(nks, ksb + hh);
+    const cpx<T>* ap = Top + (size_t)(g.side_off[f] + kb + kk) * NI + (dout >= 0 ? dout : 0);
+    const size_t astep = (size_t)4 * NI;
+    const cpx<T>* b0 = bp + (size_t)kk * 16 + jc;
+    const cpx<T>* b1 = bp + (size_t)(LMAX + kk) * 16 + jc;
     cpx<T> a0[KB], a1[KB];
     auto load = [&](cpx<T>(&a)[KB], int ks0) {
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         int ks = ks0 + u;
-        a[u] = (ks < nks && dout >= 0) ? Arow[(size_t)kdof[4 * ks + kk] * NI] : z;
+        a[u] = (ks < kse && 4 * ks + kk < kn && dout >= 0) ? ap[(size_t)ks * astep] : z;
       }
     };
     auto compute = [&](const cpx<T>(&a)[KB], int ks0) {
+      cpx<T> p0[KB], p1[KB];
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
-        int ks = ks0 + u;
-        if (ks < nks) {
-          const int k = 4 * ks + kk;
-          const cpx<T> v0 = gs[k * 8 + cc];
-          const cpx<T> v1 = gs[(KC + k) * 8 + cc];
-          acc0 = MF<T>::mfma(a[u].re, part ? v0.im : v0.re, acc0);
-          acc0 = MF<T>::mfma(a[u].im, part ? v0.re : -v0.im, acc0);
-          acc1 = MF<T>::mfma(a[u].re, part ? v1.im : v1.re, acc1);
-          acc1 = MF<T>::mfma(a[u].im, part ? v1.re : -v1.im, acc1);
+        const int ks = min(ks0 + u, nks - 1);
+        p0[u] = b0[(size_t)ks * 64];
+        p1[u] = b1[(size_t)ks * 64];
+      }
+      if (ks0 + KB <= kse) {
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+          aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
+          aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
+          aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
+          aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+          if (ks0 + u < kse) {
+            aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
+            aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
+            aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
+            aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
+          }
         }
       }
     };
-    load(a0, 0);
-    for (int ks0 = 0; ks0 < nks; ks0 += 2 * KB) {
+    load(a0, ksb);
+    for (int ks0 = ksb; ks0 < kse; ks0 += 2 * KB) {
       load(a1, ks0 + KB);
       compute(a0, ks0);
       load(a0, ks0 + 2 * KB);
-      compute(a1, ks0 + KB);
+      if (ks0 + KB < kse) compute(a1, ks0 + KB);
     }
   }
   __syncthreads();
-  // stage the 64 x 16 tile: st[col][row] complex
-  T* st = reinterpret_cast<T*>(gs);
+  // add the two halves in a fixed order and stage the 64 x 16 tile
+  T* st = reinterpret_cast<T*>(bp);              // [16][64] complex
+  T* part1 = st + 2 * 16 * 64;                   // second half's partials
+  const int cc = jc & 7, part = jc >> 3;
+  if (kh == 1) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int r = wave * 16 + MF<T>::row(lane, i);
-    st[2 * (cc * 64 + r) + part] = acc0[i];
-    st[2 * ((cc + 8) * 64 + r) + part] = acc1[i];
+    for (int i = 0; i < 4; ++i) {
+      int r = rw * 16 + MF<T>::row(lane, i);
+      part1[2 * (cc * 64 + r) + part] = aR0[i] + aI0[i];
+      part1[2 * ((cc + 8) * 64 + r) + part] = aR1[i] + aI1[i];
+    }
+  }
+  __syncthreads();
+  if (kh == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int r = rw * 16 + MF<T>::row(lane, i);
+      int i0 = 2 * (cc * 64 + r) + part, i1 = 2 * ((cc + 8) * 64 + r) + part;
+      st[i0] = (aR0[i] + aI0[i]) + part1[i0];
+      st[i1] = (aR1[i] + aI1[i]) + part1[i1];
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 2; ++q) {
     if (eo[q].dst < 0) continue;
-    int idx = tid + q * 256;
+    int idx = tid + q * 512;
     int col = idx >> 6, r = idx & 63;
-    cpx<T> v = gs[col * 64 + r] + ey[q];
+    cpx<T> v = bp[col * 64 + r] + ey[q];
     slots[eo[q].dst] = edst[q] + (v - ein[q]);
   }
 }
@@ -861,15 +892,21 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  // KC: input dofs per LDS chunk (2 tiles x KC x 8 complex = 64 KB)
-  constexpr int KC = sizeof(T) == 4 ? 512 : 256;
-  constexpr int KB = sizeof(T) == 4 ? 16 : 6;
-  dim3 grid((nout + 63) / 64, Cp / 16, cnt);
-  size_t lds = (size_t)2 * KC * 8 * sizeof(cpx<T>) + (size_t)KC * sizeof(int);
-  hipLaunchKernelGGL((k_sweep_step<T, KB, KC>), grid, dim3(256), lds, c->stream,
+  // LDS chunks of one input face (or a part of it): 2 tiles x LMAX x 16
+  // operand pairs, LMAX a multiple of 4 that keeps the chunk at <= 128 KB
+  int flen = 0;
+  for (int q = 0; q < fin.n; ++q) flen = std::max(flen, 2 * g.side_len[fin.face[q]]);
+  const int lcap = sizeof(T) == 4 ? 512 : 256;
+  const int nsub_chunks = (flen + lcap - 1) / lcap;
+  const int LMAX = ((flen + nsub_chunks - 1) / nsub_chunks + 3) / 4 * 4;
+  constexpr int KB = sizeof(T) == 4 ? 8 : 4;
+  const int nrt = (nout + 63) / 64;
+  dim3 grid(8 * ((nrt + 7) / 8) * cnt, Cp / 16, 1);
+  size_t lds = std::max<size_t>((size_t)2 * LMAX * 16, 2 * 16 * 64) * sizeof(cpx<T>);
+  hipLaunchKernelGGL((k_sweep_step<T, KB>), grid, dim3(512), lds, c->stream,
                      (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_g, (cpx<T>*)c->d_slots,
                      (const cpx<T>*)c->d_y, c->d_op_of_sub, c->d_step_subs + off, L, C, Cp,
-                     fin, nin, fout, nout, L == 0 ? 1 : 0, c->gd);
+                     fin, nin, fout, nout, L == 0 ? 1 : 0, LMAX, nsub_chunks, c->gd);
   return hipGetLastError();
 }
 

@@ -65,7 +65,9 @@ DDM_CASES = [
     (40, 6, (1, 4), 1.5, 2),
     (40, 6, (4, 1), None, 1),
     (64, 16, (4, 4), None, 1),
-    (56, 5, (2, 7), 1.5, 1),     # ragged: n_ext 38 x 18, odd sizes
+    (56, 5, (2, 7), 1.5, 1),     # ragged: n_ext 38 x 18
+    (42, 5, (2, 2), None, 1),    # odd extended size: n = K = 31
+    (45, 4, (3, 5), 1.5, 2),     # odd and unequal: n = 23, K = 17
 ]
 
 
