@@ -166,6 +166,37 @@ hdsw_status hdsw_timing_enable(hdsw_ctx* ctx, int enable);
 hdsw_status hdsw_timing_get(hdsw_ctx* ctx, int which, double* total_ms,
                             long long* launches, double* flops, double* bytes);
 
+/* Continuous batching (for a request loop): the context holds `capacity`
+ * right-hand-side slots; solves join and leave between iterations.
+ *   hdsw_batch_reserve : allocate workspaces for `capacity` columns; no
+ *       slot may be occupied.  Errors: ENOTFACTORED, EINVAL, EBUSY, ENOMEM.
+ *   hdsw_batch_add     : f_dev complex128 [nrhs][n_z][n_y][n_x] (interior
+ *       sources, caller-owned, read before return); the column starts at
+ *       x = 0, r = b; the slot ids are written to slots[nrhs] (host).
+ *       EBUSY if fewer than nrhs slots are free.
+ *   hdsw_batch_step    : enqueue one refinement iteration for every occupied
+ *       slot: x += M^{-1} r (M^{-1} = the DDM of Algorithm 2.1), then the
+ *       FP64 residual r = b - S x; returns without waiting, so steps of
+ *       several contexts on separate streams overlap on the device.
+ *   hdsw_batch_wait    : wait for the step; rel_residual (host, capacity
+ *       entries, nullable) receives ||b - S x|| / ||b|| of each occupied
+ *       slot's updated iterate, -1 for free slots and for slots added after
+ *       the step was enqueued.
+ *   hdsw_batch_ready   : non-blocking: HDSW_OK if the last step has
+ *       finished (or none is in flight), HDSW_EBUSY while it runs.
+ *   hdsw_batch_take    : copy the slot's iterate on the interior nodes to
+ *       x_dev (complex128 [n_z][n_y][n_x], nullable) and free the slot;
+ *       call it after hdsw_batch_wait.  The other slots keep their ids.
+ * A column's arithmetic does not depend on the other columns.  While any
+ * slot is occupied, hdsw_solve, hdsw_apply_precond and hdsw_residual on the
+ * same context return HDSW_EBUSY (the slots own the workspaces). */
+hdsw_status hdsw_batch_reserve(hdsw_ctx* ctx, int capacity);
+hdsw_status hdsw_batch_add(hdsw_ctx* ctx, const hdsw_c128* f_dev, int nrhs, int* slots);
+hdsw_status hdsw_batch_step(hdsw_ctx* ctx);
+hdsw_status hdsw_batch_wait(hdsw_ctx* ctx, double* rel_residual);
+hdsw_status hdsw_batch_ready(hdsw_ctx* ctx);
+hdsw_status hdsw_batch_take(hdsw_ctx* ctx, int slot, hdsw_c128* x_dev);
+
 void hdsw_destroy(hdsw_ctx* ctx);
 const char* hdsw_status_str(hdsw_status s);
 

@@ -13,6 +13,12 @@ hdsw_status solve(hdsw_ctx*, const c128*, c128*, int, hdsw_solve_info*);
 hdsw_status apply_precond(hdsw_ctx*, const c128*, c128*, int);
 hdsw_status residual(hdsw_ctx*, const c128*, const c128*, c128*, int, double*);
 hdsw_status timing_get(hdsw_ctx*, int, double*, long long*, double*, double*);
+hdsw_status batch_reserve(hdsw_ctx*, int);
+hdsw_status batch_add(hdsw_ctx*, const c128*, int, int*);
+hdsw_status batch_step(hdsw_ctx*);
+hdsw_status batch_wait(hdsw_ctx*, double*);
+hdsw_status batch_ready(hdsw_ctx*);
+hdsw_status batch_take(hdsw_ctx*, int, c128*);
 void destroy(hdsw_ctx*);
 }  // namespace hdsw
 
@@ -110,6 +116,62 @@ hdsw_status hdsw_timing_get(hdsw_ctx* ctx, int which, double* total_ms, long lon
                             double* flops, double* bytes) {
   if (!ctx) return HDSW_EINVAL;
   return hdsw::timing_get(ctx, which, total_ms, launches, flops, bytes);
+}
+
+hdsw_status hdsw_batch_reserve(hdsw_ctx* ctx, int capacity) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::batch_reserve(ctx, capacity);
+  } catch (const std::bad_alloc&) {
+    return HDSW_ENOMEM;
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_batch_add(hdsw_ctx* ctx, const hdsw_c128* f, int nrhs, int* slots) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::batch_add(ctx, reinterpret_cast<const hdsw::c128*>(f), nrhs, slots);
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_batch_step(hdsw_ctx* ctx) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::batch_step(ctx);
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_batch_wait(hdsw_ctx* ctx, double* rel_residual) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::batch_wait(ctx, rel_residual);
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_batch_ready(hdsw_ctx* ctx) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::batch_ready(ctx);
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
+}
+
+hdsw_status hdsw_batch_take(hdsw_ctx* ctx, int slot, hdsw_c128* x) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::batch_take(ctx, slot, reinterpret_cast<hdsw::c128*>(x));
+  } catch (...) {
+    return HDSW_EDEVICE;
+  }
 }
 
 void hdsw_destroy(hdsw_ctx* ctx) { hdsw::destroy(ctx); }

@@ -644,6 +644,7 @@ hdsw_status apply_precond(hdsw_ctx* c, const c128* r, c128* z, int nrhs) {
   if (c->sticky != HDSW_OK) return c->sticky;
   if (!c->factored) return HDSW_ENOTFACTORED;
   if (!r || !z || nrhs < 1) return HDSW_EINVAL;
+  if (c->nact > 0) return HDSW_EBUSY;  // batch slots own the workspaces
   int chunk = (int)std::min<size_t>(nrhs, max_cols(c));
   if (chunk < 1) return HDSW_ENOMEM;
   ACHK(ensure_ws(c, chunk, false));
@@ -659,6 +660,7 @@ hdsw_status residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, int nrh
                      double* rn) {
   if (c->sticky != HDSW_OK) return c->sticky;
   if (!b || !x || !r || nrhs < 1) return HDSW_EINVAL;
+  if (c->nact > 0) return HDSW_EBUSY;  // batch slots own the workspaces
   ACHK(ensure_ws(c, std::min(nrhs, std::max(c->Cmax, 1)), false));
   for (int c0 = 0; c0 < nrhs; c0 += c->Cmax) {
     int C = std::min(c->Cmax, nrhs - c0);
@@ -695,11 +697,18 @@ static hdsw_status refine_cols(hdsw_ctx* c, int C, std::vector<int>& iters,
     HCHK(hipStreamSynchronize(c->stream));
     bool all = true;
     for (int j = 0; j < C; ++j) {
-      rel[j] = bn[j] > 0 ? rn[j] / bn[j] : 0.0;
-      if (iters[j] < 0 && rel[j] <= c->opt.tol) iters[j] = it;
+      if (iters[j] < 0) {
+        rel[j] = bn[j] > 0 ? rn[j] / bn[j] : 0.0;
+        if (rel[j] <= c->opt.tol) iters[j] = it;
+      }
       if (iters[j] < 0) all = false;
     }
     if (all || it == c->opt.max_iter) break;
+    // a converged column takes no further update (x += M^{-1} 0 is x
+    // exactly), so its result does not depend on the other columns
+    for (int j = 0; j < C; ++j)
+      if (iters[j] >= 0)
+        HCHK(launch_zero(c, c->d_rg + (size_t)j * g.glob_nodes, g.glob_nodes * sizeof(c128)));
     ACHK(ddm(c, c->d_rg, c->d_xg, C, 1));
   }
   return HDSW_OK;
@@ -712,6 +721,7 @@ hdsw_status solve(hdsw_ctx* c, const c128* f, c128* x, int nrhs, hdsw_solve_info
   if (c->sticky != HDSW_OK) return c->sticky;
   if (!c->factored) return HDSW_ENOTFACTORED;
   if (!f || !x || nrhs < 1) return HDSW_EINVAL;
+  if (c->nact > 0) return HDSW_EBUSY;  // batch slots own the workspaces
   int chunk = (int)std::min<size_t>(nrhs, max_cols(c));
   if (chunk < 1) return HDSW_ENOMEM;
   bool gm = c->opt.gmres_m > 0;
@@ -743,6 +753,137 @@ hdsw_status solve(hdsw_ctx* c, const c128* f, c128* x, int nrhs, hdsw_solve_info
   return conv ? HDSW_OK : HDSW_ENOCONV;
 }
 
+// ------------------------------------------------------------ batching
+// Column slots for continuous batching.  Occupied slots are kept in
+// physical columns 0..nact-1 of the iterate / residual / right-hand-side
+// buffers; a slot that leaves is filled by the last occupied column.  A
+// column joins with x = 0 and r = b; a step is one refinement iteration,
+// x += M^{-1} r followed by r = b - S x, over all occupied columns, and the
+// norms of the new residuals are copied to pinned host memory for
+// batch_wait.  A slot that reports convergence can be taken at once, with
+// no further update.
+hdsw_status batch_reserve(hdsw_ctx* c, int cap) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (!c->factored) return HDSW_ENOTFACTORED;
+  if (cap < 1) return HDSW_EINVAL;
+  if (c->nact > 0) return HDSW_EBUSY;
+  ACHK(ensure_ws(c, cap, false));
+  if (!c->h_norm || cap > c->batch_cap) {
+    if (c->h_norm) (void)hipHostFree(c->h_norm);
+    c->h_norm = nullptr;
+    if (hipHostMalloc((void**)&c->h_norm, sizeof(double) * cap) != hipSuccess) {
+      c->h_norm = nullptr;
+      c->batch_cap = 0;
+      return HDSW_ENOMEM;
+    }
+  }
+  if (!c->step_done) HCHK(hipEventCreateWithFlags(&c->step_done, hipEventDisableTiming));
+  c->batch_cap = cap;
+  c->slot_of_col.assign(cap, -1);
+  c->col_of_slot.assign(cap, -1);
+  c->bnorm_slot.assign(cap, 0.0);
+  c->nact = 0;
+  c->step_cols = 0;
+  return HDSW_OK;
+}
+
+hdsw_status batch_add(hdsw_ctx* c, const c128* f, int nrhs, int* slots) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (c->batch_cap == 0) return HDSW_ENOTFACTORED;
+  if (!f || !slots || nrhs < 1) return HDSW_EINVAL;
+  if (c->nact + nrhs > c->batch_cap) return HDSW_EBUSY;
+  const size_t gn = (size_t)c->g.glob_nodes;
+  const int c0 = c->nact;
+  HCHK(launch_rhs_from_f(c, f, c->d_bg + (size_t)c0 * gn, nrhs));
+  HCHK(launch_copy_cols(c, c->d_rg + (size_t)c0 * gn, c->d_bg + (size_t)c0 * gn,
+                        (size_t)nrhs * gn));
+  HCHK(launch_zero(c, c->d_xg + (size_t)c0 * gn, (size_t)nrhs * gn * sizeof(c128)));
+  HCHK(launch_norms(c, c->d_bg + (size_t)c0 * gn, nrhs, c->d_norm));
+  std::vector<double> bn(nrhs);
+  HCHK(hipMemcpyAsync(bn.data(), c->d_norm, nrhs * sizeof(double), hipMemcpyDeviceToHost,
+                      c->stream));
+  HCHK(hipStreamSynchronize(c->stream));
+  int s = 0;
+  for (int j = 0; j < nrhs; ++j) {
+    while (c->col_of_slot[s] >= 0) ++s;
+    c->col_of_slot[s] = c0 + j;
+    c->slot_of_col[c0 + j] = s;
+    c->bnorm_slot[s] = bn[j];
+    slots[j] = s;
+  }
+  c->nact += nrhs;
+  return HDSW_OK;
+}
+
+hdsw_status batch_step(hdsw_ctx* c) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (c->batch_cap == 0) return HDSW_ENOTFACTORED;
+  const int C = c->nact;
+  c->step_cols = C;
+  if (C == 0) return HDSW_OK;
+  ACHK(ddm(c, c->d_rg, c->d_xg, C, 1));
+  {
+    TimedScope ts(c, KT_RESID, 22.0 * c->g.glob_nodes * C, 48.0 * c->g.glob_nodes * C);
+    HCHK(launch_residual(c, c->d_bg, c->d_xg, c->d_rg, C));
+  }
+  HCHK(launch_norms(c, c->d_rg, C, c->d_norm));
+  HCHK(hipMemcpyAsync(c->h_norm, c->d_norm, C * sizeof(double), hipMemcpyDeviceToHost,
+                      c->stream));
+  HCHK(hipEventRecord(c->step_done, c->stream));
+  return HDSW_OK;
+}
+
+hdsw_status batch_wait(hdsw_ctx* c, double* rel) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (c->batch_cap == 0) return HDSW_ENOTFACTORED;
+  if (c->step_cols > 0) HCHK(hipEventSynchronize(c->step_done));
+  if (rel) {
+    for (int s = 0; s < c->batch_cap; ++s) rel[s] = -1.0;
+    for (int j = 0; j < c->step_cols && j < c->nact; ++j) {
+      int s = c->slot_of_col[j];
+      rel[s] = c->bnorm_slot[s] > 0 ? c->h_norm[j] / c->bnorm_slot[s] : 0.0;
+    }
+  }
+  return HDSW_OK;
+}
+
+hdsw_status batch_ready(hdsw_ctx* c) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (c->batch_cap == 0) return HDSW_ENOTFACTORED;
+  if (c->step_cols == 0) return HDSW_OK;
+  hipError_t e = hipEventQuery(c->step_done);
+  if (e == hipErrorNotReady) return HDSW_EBUSY;
+  HCHK(e);
+  return HDSW_OK;
+}
+
+hdsw_status batch_take(hdsw_ctx* c, int slot, c128* x) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  if (c->batch_cap == 0) return HDSW_ENOTFACTORED;
+  if (slot < 0 || slot >= c->batch_cap || c->col_of_slot[slot] < 0) return HDSW_EINVAL;
+  const Geometry& g = c->g;
+  const size_t gn = (size_t)g.glob_nodes;
+  int col = c->col_of_slot[slot];
+  if (x) HCHK(launch_extract_interior(c, c->d_xg + (size_t)col * gn, x, 1));
+  int last = c->nact - 1;
+  if (col != last) {
+    HCHK(launch_copy_cols(c, c->d_xg + (size_t)col * gn, c->d_xg + (size_t)last * gn, gn));
+    HCHK(launch_copy_cols(c, c->d_bg + (size_t)col * gn, c->d_bg + (size_t)last * gn, gn));
+    HCHK(launch_copy_cols(c, c->d_rg + (size_t)col * gn, c->d_rg + (size_t)last * gn, gn));
+    int ls = c->slot_of_col[last];
+    c->slot_of_col[col] = ls;
+    c->col_of_slot[ls] = col;
+  }
+  c->slot_of_col[last] = -1;
+  c->col_of_slot[slot] = -1;
+  c->nact = last;
+  // a step in flight keeps covering the old column order: the caller waits
+  // before taking, so the step count is reset here
+  c->step_cols = 0;
+  HCHK(hipStreamSynchronize(c->stream));
+  return HDSW_OK;
+}
+
 hdsw_status timing_get(hdsw_ctx* c, int which, double* ms, long long* n, double* fl,
                        double* by) {
   if (which < 0 || which > 3) return HDSW_EINVAL;
@@ -760,6 +901,8 @@ hdsw_status timing_get(hdsw_ctx* c, int which, double* ms, long long* n, double*
 
 void destroy(hdsw_ctx* c) {
   if (!c) return;
+  if (c->h_norm) (void)hipHostFree(c->h_norm);
+  if (c->step_done) (void)hipEventDestroy(c->step_done);
   resolve_timing(c);
   auto it = pools().find(c);
   if (it != pools().end()) {

@@ -202,6 +202,16 @@ struct hdsw_ctx {
   hdsw::c128* d_Z = nullptr;        // [m][C][glob]
   hdsw::c128* d_dots = nullptr;     // [m+1][C]
   hdsw::Timing tm;
+
+  // continuous batching: occupied column slots, compacted to 0..nact-1
+  int batch_cap = 0;
+  int nact = 0;
+  std::vector<int> slot_of_col;     // physical column -> caller slot id
+  std::vector<int> col_of_slot;     // caller slot id -> physical column (-1 free)
+  std::vector<double> bnorm_slot;   // ||b|| per slot
+  double* h_norm = nullptr;         // pinned host copy of the step's norms
+  hipEvent_t step_done = nullptr;
+  int step_cols = 0;                // columns the in-flight step covers
 };
 
 namespace hdsw {
@@ -237,6 +247,7 @@ hipError_t launch_norms(hdsw_ctx* c, const c128* v, int C, double* d_out);
 hipError_t launch_extract_interior(hdsw_ctx* c, const c128* glob, c128* out,
                                    int C);
 hipError_t launch_zero(hdsw_ctx* c, void* p, size_t bytes);
+hipError_t launch_copy_cols(hdsw_ctx* c, c128* dst, const c128* src, size_t n);
 // GMRES helpers (FP64)
 hipError_t launch_dots(hdsw_ctx* c, const c128* V, int nv, const c128* w, int C,
                        c128* d_out);

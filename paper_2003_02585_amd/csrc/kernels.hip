@@ -390,6 +390,18 @@ hipError_t launch_zero(hdsw_ctx* c, void* p, size_t bytes) {
   return hipGetLastError();
 }
 
+__global__ void k_copy(c128* dst, const c128* src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+hipError_t launch_copy_cols(hdsw_ctx* c, c128* dst, const c128* src, size_t n) {
+  if (n == 0) return hipSuccess;
+  int blocks = (int)std::min<size_t>((n + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, c->stream, dst, src, n);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ GMRES (FP64)
 // dots[j][col] = sum_G conj(V_j[col][G]) w[col][G], two-pass deterministic
 __global__ void k_dots_part(const c128* V, int nv, const c128* w, int C, long long gn,

@@ -25,7 +25,8 @@ KT_SOLVE, KT_GEMM, KT_FACTOR, KT_RESID = range(4)
 EXPORTED = [
     "hdsw_default_options", "hdsw_setup", "hdsw_factor", "hdsw_solve",
     "hdsw_apply_precond", "hdsw_residual", "hdsw_query", "hdsw_timing_enable",
-    "hdsw_timing_get", "hdsw_destroy", "hdsw_status_str",
+    "hdsw_timing_get", "hdsw_destroy", "hdsw_status_str", "hdsw_batch_reserve",
+    "hdsw_batch_add", "hdsw_batch_step", "hdsw_batch_wait", "hdsw_batch_ready", "hdsw_batch_take",
 ]
 
 
@@ -87,6 +88,18 @@ def load_library(path=LIB_PATH):
                                     ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
     lib.hdsw_timing_get.restype = c_int
+    lib.hdsw_batch_reserve.argtypes = [c_void_p, c_int]
+    lib.hdsw_batch_reserve.restype = c_int
+    lib.hdsw_batch_add.argtypes = [c_void_p, c_void_p, c_int, ctypes.POINTER(c_int)]
+    lib.hdsw_batch_add.restype = c_int
+    lib.hdsw_batch_step.argtypes = [c_void_p]
+    lib.hdsw_batch_step.restype = c_int
+    lib.hdsw_batch_wait.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.hdsw_batch_wait.restype = c_int
+    lib.hdsw_batch_ready.argtypes = [c_void_p]
+    lib.hdsw_batch_ready.restype = c_int
+    lib.hdsw_batch_take.argtypes = [c_void_p, c_int, c_void_p]
+    lib.hdsw_batch_take.restype = c_int
     lib.hdsw_destroy.argtypes = [c_void_p]
     lib.hdsw_destroy.restype = None
     lib.hdsw_status_str.argtypes = [c_int]
@@ -195,6 +208,44 @@ def hdsw_timing_get(ctx, which):
     _check(_lib.hdsw_timing_get(ctx, int(which), ctypes.byref(ms), ctypes.byref(n),
                                 ctypes.byref(fl), ctypes.byref(by)), "hdsw_timing_get")
     return ms.value, n.value, fl.value, by.value
+
+
+def hdsw_batch_reserve(ctx, capacity):
+    _check(_lib.hdsw_batch_reserve(ctx, int(capacity)), "hdsw_batch_reserve")
+
+
+def hdsw_batch_add(ctx, f, nrhs):
+    """f: complex128 GPU tensor [nrhs][interior grid].  Returns the slot ids."""
+    slots = (ctypes.c_int * int(nrhs))()
+    _check(_lib.hdsw_batch_add(ctx, _dev_ptr(f, "f"), int(nrhs), slots), "hdsw_batch_add")
+    return list(slots[:])
+
+
+def hdsw_batch_step(ctx):
+    _check(_lib.hdsw_batch_step(ctx), "hdsw_batch_step")
+
+
+def hdsw_batch_wait(ctx, capacity):
+    """Returns the relative residual of every slot (-1 for free slots)."""
+    rel = (ctypes.c_double * int(capacity))()
+    _check(_lib.hdsw_batch_wait(ctx, rel), "hdsw_batch_wait")
+    return np.array(rel[:])
+
+
+def hdsw_batch_ready(ctx):
+    """True if the context's last step has finished."""
+    st = _lib.hdsw_batch_ready(ctx)
+    if st == HDSW_EBUSY:
+        return False
+    _check(st, "hdsw_batch_ready")
+    return True
+
+
+def hdsw_batch_take(ctx, slot, x=None):
+    """Copies the slot's iterate to x (complex128 GPU tensor, interior grid)
+    when given, and frees the slot."""
+    xp = _dev_ptr(x, "x") if x is not None else None
+    _check(_lib.hdsw_batch_take(ctx, int(slot), xp), "hdsw_batch_take")
 
 
 def hdsw_destroy(ctx):

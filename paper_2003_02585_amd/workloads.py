@@ -44,18 +44,29 @@ def two_layer_kappa(N, h, k_below, k_above, y_interface):
     return np.broadcast_to(layer[None, :, None], shape).copy()
 
 
+def gaussian_axis(n, h, c, sigma):
+    """exp(-(x - c)^2 / (2 sigma^2)) on the n nodes of one axis."""
+    x = node_coords(n, h)
+    return np.exp(-(x - c) ** 2 / (2.0 * sigma * sigma))
+
+
+def gaussian_mass(d, sigma):
+    """(2 pi sigma^2)^{d/2}, the normalisation of a d-dimensional Gaussian."""
+    return (2.0 * np.pi * sigma * sigma) ** (d / 2.0)
+
+
 def gaussian_source(N, h, x0, sigma):
     """f(x) = exp(-|x - x0|^2 / (2 sigma^2)) / (2 pi sigma^2)^{d/2} on the
-    interior nodes (a unit-mass smoothed point source)."""
+    interior nodes (a unit-mass smoothed point source), the product of the
+    per-axis factors taken from x upwards."""
     d = len(N)
     out = np.ones(tuple(reversed(N)))
     for a in range(d):
-        x = node_coords(N[a], h)
-        g = np.exp(-(x - x0[a]) ** 2 / (2.0 * sigma * sigma))
+        g = gaussian_axis(N[a], h, x0[a], sigma)
         shp = [1] * d
         shp[d - 1 - a] = N[a]
         out = out * g.reshape(shp)
-    return out / (2.0 * np.pi * sigma * sigma) ** (d / 2.0)
+    return out / gaussian_mass(d, sigma)
 
 
 def random_positions(n, d, seed, lo, hi):
@@ -106,3 +117,55 @@ def make(name, nrhs=None, **override):
     f = sources(Ns, h, pos, 2 * h)
     return dict(kappa=kappa, f=f, h=h, W=c["W"], P=(c["P"],) * d,
                 rounds=c["rounds"], positions=pos, k=k)
+
+
+# ---------------------------------------------------------------- serving
+# A request stream: Poisson arrivals of 2D solve requests whose operator key
+# (grid size N, subdomain size n_a, medium, points per wavelength) comes from
+# a small key space, so that factors are reused, each with R point sources.
+
+SERVE_SIZES = (256, 512, 1024, 2048)
+SERVE_SUBDOMAINS = (64, 128)
+SERVE_PPW = (8, 10, 12)
+SERVE_HEIGHTS = (0.37, 0.53, 0.71)
+SERVE_RMAX = 32
+SERVE_W = 16
+
+
+def serve_kappa(key):
+    """(kappa, h, P, W, rounds) of an operator key (N, n_a, y_interface, ppw);
+    y_interface None is the constant medium, otherwise k2 = 1.5 k1 above it
+    (one extra round of sweeps for the layered medium)."""
+    N, n_a, yi, ppw = key
+    h = 1.0 / N
+    k = 2 * np.pi / (ppw * h)
+    if yi is None:
+        kap = constant_kappa((N, N), k)
+    else:
+        kap = two_layer_kappa((N, N), h, k, 1.5 * k, yi)
+    return kap, h, (N // n_a, N // n_a), SERVE_W, (1 if yi is None else 2)
+
+
+def request_stream(n, rate, seed=SEED_BASE + 5, sizes=SERVE_SIZES, subdomains=SERVE_SUBDOMAINS,
+                   ppws=SERVE_PPW, heights=SERVE_HEIGHTS, rmax=SERVE_RMAX):
+    """n requests as dicts (rid, arrival, key, positions [R][2]); arrival
+    times are a Poisson process of the given rate (requests/s; None or inf:
+    all at time 0).  Medium: constant with probability 1/2, else two-layer
+    with a uniformly chosen interface height."""
+    rng = np.random.default_rng(seed)
+    if rate is None or not np.isfinite(rate):
+        t = np.zeros(n)
+    else:
+        t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        t -= t[0]
+    out = []
+    for i in range(n):
+        N = int(rng.choice(sizes))
+        n_a = int(rng.choice(subdomains))
+        yi = None if rng.random() < 0.5 else float(rng.choice(heights))
+        ppw = int(rng.choice(ppws))
+        R = int(rng.integers(1, rmax + 1))
+        h = 1.0 / N
+        pos = rng.uniform(12 * h, 1 - 12 * h, size=(R, 2))
+        out.append(dict(rid=i, arrival=float(t[i]), key=(N, n_a, yi, ppw), positions=pos))
+    return out

@@ -68,6 +68,8 @@ DDM_CASES = [
     (56, 5, (2, 7), 1.5, 1),     # ragged: n_ext 38 x 18
     (42, 5, (2, 2), None, 1),    # odd extended size: n = K = 31
     (45, 4, (3, 5), 1.5, 2),     # odd and unequal: n = 23, K = 17
+    (256, 4, (32, 32), None, 1), # partition of the largest serving grids
+    (256, 4, (32, 32), 1.5, 2),
 ]
 
 
@@ -220,3 +222,66 @@ def test_batch_invariance(H):
         H.hdsw_destroy(ctx)
     for i in range(4):
         assert np.array_equal(batch[i], alone[i])
+
+
+def _golden(name):
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"samples_{name}.npz")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated")
+    return np.load(p)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_c2d_full_size_against_sampled_global_solution(H, prec):
+    # the benchmarked workload at full size (1024^2, 8x8, 16 RHS), solved as
+    # the benchmark launches it, against 256 sampled values and the interior
+    # norm of the oracle's global solution (SuperLU, written by
+    # tests/golden/make_samples.py from the oracle only)
+    g = _golden("c2d")
+    w = wl.make("c2d")
+    _say(f"c2d full size {prec}")
+    p = H.HDSW_FP64 if prec == "fp64" else H.HDSW_MIXED
+    c = dict(kap=w["kappa"], h=w["h"], P=w["P"], W=w["W"])
+    ctx = _ctx(H, c, precision=p, rounds=w["rounds"], tol=1e-10)
+    try:
+        ft = torch.from_numpy(w["f"]).cuda()
+        xt = torch.zeros_like(ft)
+        info, _ = H.hdsw_solve(ctx, ft, xt, ft.shape[0])
+        x = xt.cpu().numpy().reshape(len(w["f"]), -1)
+    finally:
+        H.hdsw_destroy(ctx)
+    samp = x[:, g["index"]]
+    e = max(np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(samp, g["values"]))
+    en = np.max(np.abs(np.linalg.norm(x, axis=1) - g["norms"]) / g["norms"])
+    _say(f"  sampled rel err {e:.3e}, norm rel diff {en:.3e}, iterations {[i for i, _ in info]}")
+    assert e < 1e-8
+    assert en < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_is_batch_invariant(H, prec):
+    # refinement freezes a converged column, so a column solved inside a
+    # batch whose other columns need more iterations equals the column
+    # solved alone, bit for bit
+    c = _case(64, 16, (2, 2), None, nrhs=6, seed=23)
+    _say(f"solve batch invariance {prec}")
+    p = H.HDSW_FP64 if prec == "fp64" else H.HDSW_MIXED
+    ctx = _ctx(H, c, precision=p, tol=1e-10)
+    try:
+        ft = torch.from_numpy(c["f"]).cuda()
+        xb = torch.zeros_like(ft)
+        info, _ = H.hdsw_solve(ctx, ft, xb, 6)
+        alone, ia = [], []
+        for j in range(6):
+            xj = torch.zeros_like(ft[j:j + 1])
+            inf1, _ = H.hdsw_solve(ctx, ft[j:j + 1].contiguous(), xj, 1)
+            alone.append(xj.cpu().numpy()[0])
+            ia.append(inf1[0][0])
+        xb = xb.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    _say(f"  iterations batch {[i for i, _ in info]} alone {ia}")
+    assert [i for i, _ in info] == ia
+    for j in range(6):
+        assert np.array_equal(xb[j], alone[j])
