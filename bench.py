@@ -44,13 +44,21 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rhs", type=int, default=4)
+    ap.add_argument("--dedup", type=int, default=1,
+                    help="share factors of identical subdomain operators (0: one per subdomain)")
+    ap.add_argument("--gmres-m", type=int, default=0, help="GMRES(m) instead of refinement")
+    ap.add_argument("--rounds", type=int, default=None, help="rounds of sweeps per DDM")
+    ap.add_argument("--hbm-budget-gb", type=float, default=0.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy 5 times (HBM counter scale)")
     return ap.parse_args()
 
 
-def run_path(H, torch, w, precision, steps, warmup, tol, timing):
+def run_path(H, torch, w, precision, steps, warmup, tol, timing, a):
     stream = torch.cuda.current_stream().cuda_stream
     opt = H.hdsw_default_options(precision=precision, tol=tol, rounds=w["rounds"],
-                                 max_iter=30)
+                                 max_iter=40, dedup=a.dedup, gmres_m=a.gmres_m,
+                                 hbm_budget=int(a.hbm_budget_gb * (1 << 30)))
     ctx = H.hdsw_setup(w["kappa"], w["h"], w["P"], w["W"], opt, stream=stream)
     try:
         torch.cuda.synchronize()
@@ -118,6 +126,51 @@ def cpu_baseline(w, iters, nsample):
                         f"the FP64 path needed; factorization {t_fac:.2f} s not counted"))
 
 
+def describe(a, w, nrhs):
+    d = w["kappa"].ndim
+    N = w["kappa"].shape[-1]
+    P = "x".join(str(p) for p in w["P"])
+    kmin, kmax = float(w["kappa"].min()), float(w["kappa"].max())
+    ppw = 2 * np.pi / (kmin * w["h"])
+    med = (f"constant k, {ppw:.0f} points per wavelength" if kmax == kmin else
+           f"two-layer k, {ppw:.0f} points per wavelength below, k2/k1 = {kmax / kmin:.2f}")
+    it = f"GMRES({a.gmres_m})" if a.gmres_m else "FP64 refinement"
+    return (f"{a.config}: {d}D {N}^{d} interior, {P} subdomains, PML {w['W']}, {med}, "
+            f"{nrhs} Gaussian sources, {w['rounds']} round(s) of sweeps per DDM, {it}")
+
+
+def measured_traffic(a, dom):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary of this workload, when that summary was taken
+    on the current kernel source (sha256 of mfma.hip); else None."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"pmc_{a.config}.md")
+    src = os.path.join(ROOT, "paper_2003_02585_amd", "csrc", "mfma.hip")
+    if not os.path.exists(path) or a.dedup != 1 or a.gmres_m or a.rounds is not None:
+        return None
+    txt = open(path).read()
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    m = re.search(r"source sha256: ([0-9a-f]{64})", txt)
+    if not m or m.group(1) != h:
+        return None
+    key = "sweep_step" if dom == 1 else "block_solve"
+    m = re.search(rf"traffic_bytes_per_launch\[{key}\]: ([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    n = 512 << 20
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    x.fill_(1)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "repeats": 5}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -125,13 +178,18 @@ def main():
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
+    if a.copy_calibration:
+        copy_calibration(torch)
+        return
     from paper_2003_02585_amd import hdsw as H
     from paper_2003_02585_amd import workloads as wl
 
     w = wl.make(a.config)
-    mixed = run_path(H, torch, w, H.HDSW_MIXED, a.steps, a.warmup, a.tol, True)
+    if a.rounds is not None:
+        w["rounds"] = a.rounds
+    mixed = run_path(H, torch, w, H.HDSW_MIXED, a.steps, a.warmup, a.tol, True, a)
     fsteps = a.fp64_steps if a.fp64_steps is not None else max(1, a.steps // 2)
-    fp64 = run_path(H, torch, w, H.HDSW_FP64, fsteps, 1, a.tol, False)
+    fp64 = run_path(H, torch, w, H.HDSW_FP64, fsteps, 1, a.tol, False, a)
     nrhs = mixed["nrhs"]
     value = nrhs * a.steps / mixed["total"]
     v64 = nrhs * fsteps / fp64["total"]
@@ -157,7 +215,8 @@ def main():
     dom = max((0, 1), key=lambda k: kt[k][0])
     d = kernels[names[dom]]
     roof = {"bound": "mfma", "achieved": d["achieved_TFLOPs"], "peak": peak, "unit": "TFLOP/s",
-            "frac": round(d["achieved_TFLOPs"] / peak, 4), "traffic": None,
+            "frac": round(d["achieved_TFLOPs"] / peak, 4),
+            "traffic": measured_traffic(a, dom),
             "kernel": names[dom], "avg_launch_ms": d["avg_launch_ms"],
             "launches": d["launches"]}
     iters64 = max(i for i, _ in fp64["info"])
@@ -170,9 +229,9 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(float(lat.mean()), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
         "data": "synthetic",
-        "config": {"workload": f"{a.config}: 2D {w['kappa'].shape[1]}^2, 8x8 subdomains, "
-                               f"PML {w['W']}, 10 ppw, {nrhs} Gaussian sources, 1 round",
-                   "nrhs": nrhs, "tol": a.tol},
+        "config": {"workload": describe(a, w, nrhs), "nrhs": nrhs, "tol": a.tol,
+                   "rounds": w["rounds"], "dedup": a.dedup, "gmres_m": a.gmres_m,
+                   "distinct_operators": mixed["nops"]},
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "fp64_value": round(v64, 3), "speedup_mixed_vs_fp64": round(value / v64, 3),

@@ -1,5 +1,6 @@
 """Write sampled values of the global PML solution u_glob = S^{-1} b for the
-full-size workloads (FP64 oracle, SuperLU), for full-size GPU parity tests.
+full-size workloads (FP64 oracle: SuperLU with two steps of FP64 iterative
+refinement), for full-size GPU parity tests.
 
 Calls only the oracle and the seeded input module.  For every RHS of the
 workload it stores u_glob at 256 interior nodes drawn with a fixed seed and
@@ -41,6 +42,9 @@ def main(name):
     for j, fj in enumerate(w["f"]):
         b = O.global_rhs(prob, fj).ravel()
         u = lu.solve(b)
+        for _ in range(2):
+            # FP64 iterative refinement of the direct solve
+            u = u + lu.solve(b - S @ u)
         resid[j] = np.linalg.norm(b - S @ u) / np.linalg.norm(b)
         ui = u.reshape(prob.gshape)[sl].ravel()
         vals[j] = ui[flat]
