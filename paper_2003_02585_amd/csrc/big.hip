@@ -1,0 +1,478 @@
+// Dense-block path of the hdsw library, used when one block of the
+// subdomain operator is a whole grid plane (3D: n = n_x n_y, K = n_z).
+//
+// Block-tridiagonal LU with the coupling B_k = diag(a^z) between planes
+// k-1 and k (the operator is complex symmetric, so the coupling is the same
+// on both sides of the diagonal):
+//   D_0 = A_0,   D_k = A_k - B_k D_{k-1}^{-1} B_k,   X_k = D_k^{-1}
+// and, for every right-hand side,
+//   forward   w_0 = X_0 f_0,   w_k = X_k (f_k - B_k w_{k-1})
+//   backward  x_{K-1} = w_{K-1},   x_k = w_k - X_k (B_{k+1} x_{k+1}).
+// X_k is formed by blocked Gauss-Jordan elimination with partial pivoting
+// (largest |Re| + |Im| in the column, lowest row index on ties): a panel of
+// nb columns is eliminated by one workgroup, the rest of the matrix is
+// updated by one complex GEMM, and the column order is restored at the end.
+// Every product with a dense block is a complex GEMM on the matrix cores
+// (k_cgemm).
+#include "hdsw_internal.hpp"
+#include "mfma_ops.hpp"
+
+namespace hdsw {
+
+// ------------------------------------------------------------ complex GEMM
+// C_z = beta C_z + s A_z B_z  (s = +1 or -1, beta = 0 or 1), complex, all
+// column-major.  z indexes a group of columns that share one A:
+//   A_z        = A + op_z * sAz,            op_z = grp_op ? grp_op[z] : z
+//   column j of B_z (j < ncols_z): B + z * sBz + e * sb + (j % cpb) * ldb,
+//     e = ids ? ids[off_z + j / cpb] : j / cpb,  off_z = grp_off ? grp_off[z] : 0
+//   C the same with sCz, sc, ldc,
+//   ncols_z = grp_cnt ? grp_cnt[z] * cpb : N.
+// A workgroup computes a 64 x 32 tile of C with four waves, one 16-row
+// strip each; the sum runs in chunks of 16 staged in LDS.  A complex
+// product takes two real MFMAs per 16 x 16 x 4 step: B is staged as pairs
+// (Re b, -Im b) and (Im b, Re b) in the two halves of a 16-wide operand, so
+// that Re(A) x first + Im(A) x second gives [Re(AB) | Im(AB)] for 8 complex
+// columns.
+struct GemmArgs {
+  int M, N, Kd;
+  const void* A;
+  long long lda, sAz;
+  const void* B;
+  long long ldb, sb, sBz;
+  void* C;
+  long long ldc, sc, sCz;
+  int cpb;
+  const int* ids;
+  const int* grp_op;
+  const int* grp_off;
+  const int* grp_cnt;
+  int neg;
+  int beta;
+};
+
+constexpr int GM = 64, GN = 32, GK = 16, GPAD = 80;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
+  typedef typename MF<T>::v4 v4;
+  __shared__ cpx<T> As[GK][GPAD];        // [k][row]
+  __shared__ cpx<T> Bp[GK][GPAD];        // [k][4 groups x 16 operand columns]
+  __shared__ cpx<T> Cs[GN][GM];          // [col][row] epilogue staging
+  const int z = blockIdx.z;
+  const int ncols = a.grp_cnt ? a.grp_cnt[z] * a.cpb : a.N;
+  const int col0 = blockIdx.y * GN;
+  if (col0 >= ncols) return;
+  const int row0 = blockIdx.x * GM;
+  const int opz = a.grp_op ? a.grp_op[z] : z;
+  const int off = a.grp_off ? a.grp_off[z] : 0;
+  const cpx<T>* A = reinterpret_cast<const cpx<T>*>(a.A) + (long long)opz * a.sAz;
+  const cpx<T>* B = reinterpret_cast<const cpx<T>*>(a.B) + (long long)z * a.sBz;
+  cpx<T>* C = reinterpret_cast<cpx<T>*>(a.C) + (long long)z * a.sCz;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const cpx<T> zero = mk<T>(T(0), T(0));
+
+  // this thread's B column for loading: 2 consecutive k of column bc
+  const int bc = tid >> 3, bk = (tid & 7) * 2;
+  const cpx<T>* bcol = nullptr;
+  {
+    int j = col0 + bc;
+    if (j < ncols) {
+      int e = j / a.cpb, jj = j - e * a.cpb;
+      int eid = a.ids ? a.ids[off + e] : e;
+      bcol = B + (long long)eid * a.sb + (long long)jj * a.ldb;
+    }
+  }
+  // A rows: row ar, k = ak .. ak + 3
+  const int ar = tid & 63, ak = (tid >> 6) * 4;
+  const bool arow_ok = row0 + ar < a.M;
+  const cpx<T>* acol = A + row0 + ar;
+
+  cpx<T> ra[4], rb[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int k = k0 + ak + u;
+      ra[u] = (arow_ok && k < a.Kd) ? acol[(long long)k * a.lda] : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int k = k0 + bk + u;
+      rb[u] = (bcol && k < a.Kd) ? bcol[k] : zero;
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) As[ak + u][ar] = ra[u];
+    const int g = bc >> 3, cc = bc & 7;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      Bp[bk + u][g * 16 + cc] = mk<T>(rb[u].re, -rb[u].im);
+      Bp[bk + u][g * 16 + cc + 8] = mk<T>(rb[u].im, rb[u].re);
+    }
+  };
+
+  v4 accR[4], accI[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    accR[g] = v4{T(0), T(0), T(0), T(0)};
+    accI[g] = accR[g];
+  }
+  const int mr = wave * 16 + (lane & 15), mk4 = lane >> 4, mc = lane & 15;
+  gload(0);
+  for (int k0 = 0; k0 < a.Kd; k0 += GK) {
+    __syncthreads();
+    lstore();
+    __syncthreads();
+    if (k0 + GK < a.Kd) gload(k0 + GK);
+#pragma unroll
+    for (int ks = 0; ks < GK / 4; ++ks) {
+      const cpx<T> av = As[ks * 4 + mk4][mr];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const cpx<T> p = Bp[ks * 4 + mk4][g * 16 + mc];
+        accR[g] = MF<T>::mfma(av.re, p.re, accR[g]);
+        accI[g] = MF<T>::mfma(av.im, p.im, accI[g]);
+      }
+    }
+  }
+  // stage [Re | Im] halves as complex columns
+  T* cs = reinterpret_cast<T*>(&Cs[0][0]);
+  const int part = mc >> 3, cc = mc & 7;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int r = wave * 16 + MF<T>::row(lane, i);
+      cs[2 * ((g * 8 + cc) * GM + r) + part] = accR[g][i] + accI[g][i];
+    }
+  }
+  __syncthreads();
+  const int orow = tid & 63, oc = tid >> 6;
+  if (row0 + orow >= a.M) return;
+#pragma unroll
+  for (int q = 0; q < GN / 4; ++q) {
+    int c = oc * (GN / 4) + q;
+    int j = col0 + c;
+    if (j >= ncols) break;
+    int e = j / a.cpb, jj = j - e * a.cpb;
+    int eid = a.ids ? a.ids[off + e] : e;
+    cpx<T>* dst = C + (long long)eid * a.sc + (long long)jj * a.ldc + row0 + orow;
+    cpx<T> v = Cs[c][orow];
+    if (a.neg) v = -v;
+    if (a.beta) v = *dst + v;
+    *dst = v;
+  }
+}
+
+template <class T>
+static hipError_t gemm(hipStream_t st, const GemmArgs& a, int maxcols, int ngroups) {
+  if (a.M <= 0 || maxcols <= 0 || ngroups <= 0) return hipSuccess;
+  dim3 grid((a.M + GM - 1) / GM, (maxcols + GN - 1) / GN, ngroups);
+  hipLaunchKernelGGL(k_cgemm<T>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ Gauss-Jordan
+// One workgroup per matrix z (X + z * sz, n x n column-major) eliminates the
+// pivots j0 .. j0 + nbr - 1, touching whole rows for the swaps and the
+// panel columns for the elimination.  piv[z * n + kc] records the row
+// swapped into position kc.
+template <class T>
+__global__ __launch_bounds__(1024) void k_gj_panel(cpx<T>* X, long long sz, int n, int j0,
+                                                   int nbr, int* piv, int* flag) {
+  __shared__ float bestv[1024];
+  __shared__ int besti[1024];
+  __shared__ cpx<T> prow[64];
+  const int tid = threadIdx.x;
+  cpx<T>* A = X + (long long)blockIdx.x * sz;
+  for (int kc = j0; kc < j0 + nbr; ++kc) {
+    // pivot: largest |Re| + |Im| at or below the diagonal, lowest index on ties
+    float bv = -1.f;
+    int bi = n;
+    for (int i = kc + tid; i < n; i += 1024) {
+      cpx<T> v = A[(long long)kc * n + i];
+      float m = (float)(fabs(v.re) + fabs(v.im));
+      if (m > bv) { bv = m; bi = i; }
+    }
+    bestv[tid] = bv;
+    besti[tid] = bi;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+      if (tid < w) {
+        float ov = bestv[tid + w];
+        int oi = besti[tid + w];
+        if (ov > bestv[tid] || (ov == bestv[tid] && oi < besti[tid])) {
+          bestv[tid] = ov;
+          besti[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int r = besti[0];
+    const bool singular = !(bestv[0] > 0.f) || r >= n;
+    __syncthreads();
+    if (tid == 0) {
+      piv[(long long)blockIdx.x * n + kc] = singular ? kc : r;
+      if (singular) flag[0] = 1;
+    }
+    if (!singular && r != kc) {
+      for (int j = tid; j < n; j += 1024) {
+        cpx<T> t = A[(long long)j * n + kc];
+        A[(long long)j * n + kc] = A[(long long)j * n + r];
+        A[(long long)j * n + r] = t;
+      }
+    }
+    __syncthreads();
+    const cpx<T> pv = A[(long long)kc * n + kc];
+    const cpx<T> ip = singular ? mk<T>(T(0), T(0)) : cinv(pv);
+    if (tid < nbr) {
+      int j = j0 + tid;
+      cpx<T> v = A[(long long)j * n + kc];
+      prow[tid] = j == kc ? ip : v * ip;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+      if (i == kc) continue;
+      cpx<T> f = A[(long long)kc * n + i];
+      for (int q = 0; q < nbr; ++q) {
+        int j = j0 + q;
+        if (j == kc) {
+          A[(long long)j * n + i] = -(f * ip);
+        } else {
+          cpx<T> v = A[(long long)j * n + i];
+          A[(long long)j * n + i] = v - f * prow[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < nbr) A[(long long)(j0 + tid) * n + kc] = prow[tid];
+    __syncthreads();
+  }
+}
+
+// R_z[q][j] = A_z[j0 + q][j] for j outside the panel (0 inside), those
+// entries of A_z set to zero, and E_z = the eliminated panel columns: the
+// rest of the matrix is then A += E R.  R is nbr x n (leading dimension
+// nbr), E is n x nbr (leading dimension n); they sit at R + z sR and
+// R + z sR + n nbr_max.
+template <class T>
+__global__ void k_gj_take_rows(cpx<T>* X, long long sz, int n, int j0, int nbr, cpx<T>* R,
+                               long long sR, long long eoff) {
+  cpx<T>* A = X + (long long)blockIdx.y * sz;
+  cpx<T>* Rz = R + (long long)blockIdx.y * sR;
+  cpx<T>* Ez = Rz + eoff;
+  long long tot = (long long)n * nbr;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int j = (int)(idx / nbr), q = (int)(idx - (long long)j * nbr);
+    cpx<T>* src = A + (long long)j * n + j0 + q;
+    if (j >= j0 && j < j0 + nbr) {
+      Rz[idx] = mk<T>(T(0), T(0));
+    } else {
+      Rz[idx] = *src;
+      *src = mk<T>(T(0), T(0));
+    }
+    // panel column j0 + q, row j (rows of the panel columns are not zeroed)
+    Ez[(long long)q * n + j] = A[(long long)(j0 + q) * n + j];
+  }
+}
+
+// undo the row interchanges on the columns of the inverse, last first
+template <class T>
+__global__ void k_gj_colperm(cpx<T>* X, long long sz, int n, const int* piv) {
+  cpx<T>* A = X + (long long)blockIdx.y * sz;
+  const int* pz = piv + (long long)blockIdx.y * n;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int kc = n - 1; kc >= 0; --kc) {
+    int r = pz[kc];
+    if (r != kc) {
+      cpx<T> t = A[(long long)kc * n + i];
+      A[(long long)kc * n + i] = A[(long long)r * n + i];
+      A[(long long)r * n + i] = t;
+    }
+  }
+}
+
+// ------------------------------------------------------------ factor
+// Dense D_k of every distinct operator (3D, plane k) written into its X_k
+// slot: the in-plane 5-point part of the operator minus
+// B_k X_{k-1} B_k (k > 0).  Coefficients per operator:
+//   ax[n_z][n_y][n_x + 1], ay[n_z][n_y + 1][n_x], az[n_z + 1][n_y][n_x], dg[n_z][n_y][n_x]
+template <class T>
+__global__ void k_form_plane(cpx<T>* X, const cpx<T>* coefT, size_t cstride, GeoDev g,
+                             int k, int nops) {
+  const int nx = g.ne[0], ny = g.ne[1], nz = g.ne[2];
+  const int n = g.n;
+  const long long nn = (long long)n * n;
+  const size_t o_ay = (size_t)nz * ny * (nx + 1);
+  const size_t o_az = o_ay + (size_t)nz * (ny + 1) * nx;
+  const size_t o_dg = o_az + (size_t)(nz + 1) * ny * nx;
+  const int op = blockIdx.y;
+  if (op >= nops) return;
+  const cpx<T>* co = coefT + (size_t)op * cstride;
+  cpx<T>* Xk = X + ((long long)op * g.K + k) * nn;
+  const cpx<T>* Xp = Xk - nn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < nn;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int j = (int)(idx / n), i = (int)(idx - (long long)j * n);
+    int yi = i / nx, xi = i - yi * nx;
+    int yj = j / nx, xj = j - yj * nx;
+    cpx<T> v = mk<T>(T(0), T(0));
+    if (i == j) v = co[o_dg + ((size_t)k * ny + yi) * nx + xi];
+    else if (yi == yj && xj == xi + 1) v = co[((size_t)k * ny + yi) * (nx + 1) + xi + 1];
+    else if (yi == yj && xj == xi - 1) v = co[((size_t)k * ny + yi) * (nx + 1) + xi];
+    else if (xi == xj && yj == yi + 1) v = co[o_ay + ((size_t)k * (ny + 1) + yi + 1) * nx + xi];
+    else if (xi == xj && yj == yi - 1) v = co[o_ay + ((size_t)k * (ny + 1) + yi) * nx + xi];
+    if (k > 0) {
+      cpx<T> bi = co[o_az + ((size_t)k * ny + yi) * nx + xi];
+      cpx<T> bj = co[o_az + ((size_t)k * ny + yj) * nx + xj];
+      v = v - bi * Xp[idx] * bj;
+    }
+    Xk[idx] = v;
+  }
+}
+
+// rbuf: 2 n 32 elements per distinct operator (panel rows R and columns E)
+template <class T>
+hipError_t launch_big_factor(hdsw_ctx* c, void* rbuf) {
+  const Geometry& g = c->g;
+  const int n = g.n, nops = c->nops;
+  const long long nn = (long long)n * n;
+  const long long sz = (long long)g.K * nn;     // operator stride in X
+  cpx<T>* X = (cpx<T>*)c->d_X;
+  cpx<T>* R = (cpx<T>*)rbuf;
+  const int nb = 32;
+  for (int k = 0; k < g.K; ++k) {
+    int blocks = (int)std::min<long long>((nn + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(k_form_plane<T>, dim3(blocks, nops), dim3(256), 0, c->stream, X,
+                       (const cpx<T>*)c->d_coefT, c->coef_stride, c->gd, k, nops);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cpx<T>* Xk = X + (long long)k * nn;
+    int* piv = c->d_piv;
+    for (int j0 = 0; j0 < n; j0 += nb) {
+      int nbr = std::min(nb, n - j0);
+      hipLaunchKernelGGL(k_gj_panel<T>, dim3(nops), dim3(1024), 0, c->stream, Xk, sz, n, j0,
+                         nbr, piv, c->d_flag);
+      long long tot = (long long)n * nbr;
+      int tb = (int)std::min<long long>((tot + 255) / 256, 1 << 16);
+      hipLaunchKernelGGL(k_gj_take_rows<T>, dim3(tb, nops), dim3(256), 0, c->stream, Xk, sz,
+                         n, j0, nbr, R, 2LL * n * nb, (long long)n * nb);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      GemmArgs a{};
+      a.M = n;
+      a.N = n;
+      a.Kd = nbr;
+      a.A = R + (long long)n * nb;
+      a.lda = n;
+      a.sAz = 2LL * n * nb;
+      a.B = R;
+      a.ldb = nbr;
+      a.sb = 0;
+      a.sBz = 2LL * n * nb;
+      a.C = Xk;
+      a.ldc = n;
+      a.sc = 0;
+      a.sCz = sz;
+      a.cpb = n;
+      a.neg = 0;
+      a.beta = 1;
+      e = gemm<T>(c->stream, a, n, nops);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_gj_colperm<T>, dim3((n + 255) / 256, nops), dim3(256), 0, c->stream,
+                       Xk, sz, n, piv);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------ solve
+// scratch line K of each panel entry b (operator ops[b]):
+//   forward  t = f_k - B_k w_{k-1}  (k > 0),  t = f_0
+//   backward t = B_{k+1} x_{k+1}
+template <class T>
+__global__ void k_plane_rhs(cpx<T>* panel, int nbatch, int C, int k, int fwd,
+                            const int* ops, const cpx<T>* coefT, size_t cstride, GeoDev g) {
+  const int n = g.n, K = g.K;
+  const int nx = g.ne[0], ny = g.ne[1], nz = g.ne[2];
+  const size_t o_az = (size_t)nz * ny * (nx + 1) + (size_t)nz * (ny + 1) * nx;
+  const long long per = (long long)C * n;
+  const long long tot = per * nbatch;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int b = (int)(idx / per);
+    long long r = idx - b * per;
+    int p = (int)(r % n);
+    cpx<T>* base = panel + (long long)b * (K + 1) * per;
+    const cpx<T>* az = coefT + (size_t)ops[b] * cstride + o_az;
+    cpx<T> v;
+    if (fwd) {
+      v = base[(long long)k * per + r];
+      if (k > 0) v = v - az[(size_t)k * n + p] * base[(long long)(k - 1) * per + r];
+    } else {
+      v = az[(size_t)(k + 1) * n + p] * base[(long long)(k + 1) * per + r];
+    }
+    base[(long long)K * per + r] = v;
+  }
+}
+
+template <class T>
+hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int* grp_op,
+                            const int* grp_off, const int* grp_cnt, const int* ids,
+                            int ngroups, int maxcnt, int C) {
+  const Geometry& g = c->g;
+  const int n = g.n, K = g.K;
+  const long long nn = (long long)n * n;
+  const long long per = (long long)C * n;
+  cpx<T>* P = (cpx<T>*)c->d_panel;
+  long long tot = per * nbatch;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int fwd = pass == 0;
+    for (int s = 0; s < (fwd ? K : K - 1); ++s) {
+      const int k = fwd ? s : K - 2 - s;
+      hipLaunchKernelGGL(k_plane_rhs<T>, dim3(blocks), dim3(256), 0, c->stream, P, nbatch, C,
+                         k, fwd, d_ops, (const cpx<T>*)c->d_coefT, c->coef_stride, c->gd);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      GemmArgs a{};
+      a.M = n;
+      a.N = 0;
+      a.Kd = n;
+      a.A = (const cpx<T>*)c->d_X + (long long)k * nn;
+      a.lda = n;
+      a.sAz = (long long)K * nn;
+      a.B = P + (long long)K * per;
+      a.ldb = n;
+      a.sb = (long long)(K + 1) * per;
+      a.sBz = 0;
+      a.C = P + (long long)k * per;
+      a.ldc = n;
+      a.sc = (long long)(K + 1) * per;
+      a.sCz = 0;
+      a.cpb = C;
+      a.ids = ids;
+      a.grp_op = grp_op;
+      a.grp_off = grp_off;
+      a.grp_cnt = grp_cnt;
+      a.neg = fwd ? 0 : 1;
+      a.beta = fwd ? 0 : 1;
+      e = gemm<T>(c->stream, a, maxcnt * C, ngroups);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+#define HDSW_INST3(T)                                                                      \
+  template hipError_t launch_big_factor<T>(hdsw_ctx*, void*);                              \
+  template hipError_t launch_big_solve<T>(hdsw_ctx*, int, const int*, const int*,          \
+                                          const int*, const int*, const int*, int, int, int);
+HDSW_INST3(float)
+HDSW_INST3(double)
+
+}  // namespace hdsw

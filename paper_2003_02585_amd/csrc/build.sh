@@ -7,14 +7,16 @@ flags=(-O3 -std=c++17 -fPIC --offload-arch=gfx950
        -Xclang -target-feature -Xclang -packed-fp32-ops
        -Wall -Wno-unused-result -Wno-pass-failed)
 objs=()
+pids=()
 tmp="$(mktemp -d)"
 trap 'rm -rf "$tmp"' EXIT
-for src in kernels.hip mfma.hip driver.cpp krylov.cpp api.cpp; do
+for src in kernels.hip mfma.hip big.hip driver.cpp krylov.cpp api.cpp; do
   o="${tmp}/${src%.*}.o"
   hipcc "${flags[@]}" -x hip -c "${here}/${src}" -o "$o" &
   objs+=("$o")
+  pids+=($!)
 done
-wait
+for p in "${pids[@]}"; do wait "$p"; done
 hipcc --offload-arch=gfx950 -shared -fPIC "${objs[@]}" -o "${out}.tmp"
 mv "${out}.tmp" "$out"
 echo "built $out"

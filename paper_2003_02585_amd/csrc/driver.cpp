@@ -247,7 +247,7 @@ static void resolve_timing(hdsw_ctx* c) {
 hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_partition* part,
                        int W, const hdsw_options* opt, void* stream, hdsw_ctx** out) {
   if (!grid || !kappa || !part || !opt || !out) return HDSW_EINVAL;
-  if (grid->dim != 2) return HDSW_EINVAL;  // 3D sweeps are not built
+  if (grid->dim != 2 && grid->dim != 3) return HDSW_EINVAL;
   if (!(grid->h > 0) || !std::isfinite(grid->h) || W < 1) return HDSW_EINVAL;
   if (opt->precision != HDSW_FP64 && opt->precision != HDSW_MIXED) return HDSW_EINVAL;
   if (opt->rounds < 1 || opt->rounds > 4 || !(opt->pml_R > 0 && opt->pml_R < 1) ||
@@ -281,18 +281,34 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
     g.glob_nodes *= g.M[a];
   }
   g.int_nodes = nint;
-  g.n = g.ne[0];
-  g.K = g.ne[1];
+  if (g.dim == 2) {
+    g.n = g.ne[0];
+    g.K = g.ne[1];
+  } else {
+    g.n = g.ne[0] * g.ne[1];
+    g.K = g.ne[2];
+  }
   g.nP = (g.n + 15) / 16 * 16;
   g.mid = g.K / 2;
-  // the block solver keeps an nP-long vector per column in LDS
-  if (g.nP > 256) {
+  // the 2D block solver keeps an nP-long vector per column in LDS; 3D plane
+  // blocks go through the dense-block path
+  if (g.dim == 2 && g.nP > 256) {
     delete c;
     return HDSW_EINVAL;
   }
+  if (g.dim == 3 && (long long)g.n * 6 * 2 * g.n > (1LL << 31)) {
+    delete c;
+    return HDSW_EINVAL;  // interface response too large for 32-bit offsets
+  }
   g.nsides = 2 * g.dim;
-  g.side_len[0] = g.side_len[1] = g.ne[1];
-  g.side_len[2] = g.side_len[3] = g.ne[0];
+  if (g.dim == 2) {
+    g.side_len[0] = g.side_len[1] = g.ne[1];
+    g.side_len[2] = g.side_len[3] = g.ne[0];
+  } else {
+    g.side_len[0] = g.side_len[1] = g.ne[1] * g.ne[2];
+    g.side_len[2] = g.side_len[3] = g.ne[0] * g.ne[2];
+    g.side_len[4] = g.side_len[5] = g.ne[0] * g.ne[1];
+  }
   int off = 0;
   for (int s = 0; s < g.nsides; ++s) {
     g.side_off[s] = off;
@@ -349,13 +365,19 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   for (int s = 0; s < g.nsub; ++s) {
     int cc[3];
     g.sub_coords(s, cc);
-    for (int k = 0; k < g.ne[1]; ++k) {
-      int iy = std::min(std::max(cc[1] * g.na[1] + k - W, cc[1] * g.na[1]),
-                        (cc[1] + 1) * g.na[1] - 1);
-      for (int p = 0; p < g.ne[0]; ++p) {
-        int ix = std::min(std::max(cc[0] * g.na[0] + p - W, cc[0] * g.na[0]),
-                          (cc[0] + 1) * g.na[0] - 1);
-        ks[(size_t)k * g.ne[0] + p] = c->kappa[(size_t)iy * g.N[0] + ix];
+    auto clampi = [&](int a, int l) {
+      return std::min(std::max(cc[a] * g.na[a] + l - W, cc[a] * g.na[a]), (cc[a] + 1) * g.na[a] - 1);
+    };
+    const int nz = g.dim == 3 ? g.ne[2] : 1;
+    for (int lz = 0; lz < nz; ++lz) {
+      int iz = g.dim == 3 ? clampi(2, lz) : 0;
+      for (int k = 0; k < g.ne[1]; ++k) {
+        int iy = clampi(1, k);
+        for (int p = 0; p < g.ne[0]; ++p) {
+          int ix = clampi(0, p);
+          ks[((size_t)lz * g.ne[1] + k) * g.ne[0] + p] =
+              c->kappa[((size_t)iz * g.N[1] + iy) * g.N[0] + ix];
+        }
       }
     }
     int op = -1;
@@ -401,8 +423,14 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   };
   hdsw_status st;
   size_t e = elt(c);
-  c->coef_stride = (size_t)g.K * (g.n + 1) + (size_t)(g.K + 1) * g.n + (size_t)g.K * g.n;
-  size_t xbytes = (size_t)c->nops * g.K * g.nP * g.nP * e;
+  if (g.dim == 2) {
+    c->coef_stride = (size_t)g.K * (g.n + 1) + (size_t)(g.K + 1) * g.n + (size_t)g.K * g.n;
+  } else {
+    const size_t nx = g.ne[0], ny = g.ne[1], nz = g.ne[2];
+    c->coef_stride = nz * ny * (nx + 1) + nz * (ny + 1) * nx + (nz + 1) * ny * nx + nz * ny * nx;
+  }
+  size_t xbytes = g.dim == 2 ? (size_t)c->nops * g.K * g.nP * g.nP * e
+                             : (size_t)c->nops * g.K * g.n * g.n * e;
   size_t tbytes = (size_t)c->nops * g.NI * g.NI * e;
   c->factor_bytes = xbytes + tbytes;
   void* p;
@@ -426,6 +454,25 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   SALLOC(c->d_all_subs, g.nsub * sizeof(int));
   SALLOC(c->d_all_ops, c->nops * sizeof(int));
   SALLOC(c->d_flag, sizeof(int));
+  SALLOC(c->d_zero_int, sizeof(int));
+  SALLOC(c->d_one_int, sizeof(int));
+  SALLOC(c->d_piv, (size_t)c->nops * g.n * sizeof(int));
+  // subdomains grouped by operator (plane-block solves share one GEMM per
+  // operator and plane)
+  std::vector<int> grp_op, grp_off, grp_cnt, grp_ids;
+  for (int o = 0; o < c->nops; ++o) {
+    grp_op.push_back(o);
+    grp_off.push_back((int)grp_ids.size());
+    for (int s = 0; s < g.nsub; ++s)
+      if (c->op_of_sub[s] == o) grp_ids.push_back(s);
+    grp_cnt.push_back((int)grp_ids.size() - grp_off.back());
+    c->grp_maxcnt = std::max(c->grp_maxcnt, grp_cnt.back());
+  }
+  c->ngrp = c->nops;
+  SALLOC(c->d_grp_op, c->ngrp * sizeof(int));
+  SALLOC(c->d_grp_off, c->ngrp * sizeof(int));
+  SALLOC(c->d_grp_cnt, c->ngrp * sizeof(int));
+  SALLOC(c->d_grp_ids, g.nsub * sizeof(int));
   std::vector<int> iota_s(g.nsub), iota_o(c->nops);
   for (int i = 0; i < g.nsub; ++i) iota_s[i] = i;
   for (int i = 0; i < c->nops; ++i) iota_o[i] = i;
@@ -444,6 +491,13 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   up(c->d_step_subs, c->sch.step_subs.data(), c->sch.step_subs.size() * sizeof(int));
   up(c->d_all_subs, iota_s.data(), g.nsub * sizeof(int));
   up(c->d_all_ops, iota_o.data(), c->nops * sizeof(int));
+  const int zero_one[2] = {0, 1};
+  up(c->d_zero_int, &zero_one[0], sizeof(int));
+  up(c->d_one_int, &zero_one[1], sizeof(int));
+  up(c->d_grp_op, grp_op.data(), c->ngrp * sizeof(int));
+  up(c->d_grp_off, grp_off.data(), c->ngrp * sizeof(int));
+  up(c->d_grp_cnt, grp_cnt.data(), c->ngrp * sizeof(int));
+  up(c->d_grp_ids, grp_ids.data(), g.nsub * sizeof(int));
   if (he != hipSuccess) return fail(HDSW_EDEVICE);
   c->part_blocks = 256;
   *out = c;
@@ -458,7 +512,7 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
   HCHK(launch_assemble(c));
   HCHK(launch_cast_coef<T>(c));
   HCHK(launch_face_coef<T>(c));
-  {
+  if (g.dim == 2) {
     double fl = 8.0 * g.n * (double)g.n * g.n * g.K * c->nops;
     double by = 2.0 * g.K * (double)g.n * g.n * sizeof(cpx<T>) * c->nops;
     TimedScope ts(c, KT_FACTOR, fl, by);
@@ -466,6 +520,20 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
     int steps = std::max(g.mid, g.K - 1 - g.mid);
     for (int st = 0; st < steps; ++st) HCHK(launch_factor_step<T>(c, st, 0));
     HCHK(launch_factor_step<T>(c, 0, 1));
+  } else {
+    // plane blocks: one dense inversion per plane, all operators together
+    void* rbuf = nullptr;
+    ACHK(dev_alloc(c, &rbuf, (size_t)c->nops * 2 * g.n * 32 * sizeof(cpx<T>)));
+    hipError_t fe;
+    {
+      double fl = 8.0 * g.n * (double)g.n * g.n * g.K * c->nops;
+      double by = 2.0 * g.K * (double)g.n * g.n * sizeof(cpx<T>) * c->nops;
+      TimedScope ts(c, KT_FACTOR, fl, by);
+      fe = launch_big_factor<T>(c, rbuf);
+    }
+    if (fe == hipSuccess) fe = hipStreamSynchronize(c->stream);
+    dev_free(c, rbuf);
+    HCHK(fe);
   }
   // interface-to-interface response T = P_I S^{-1} P_I^T of every distinct
   // operator: block solves with unit sources on the interface dofs

@@ -176,9 +176,19 @@ struct hdsw_ctx {
   int alpha_glob_off[6] = {0};
   double* d_kappa_sub = nullptr;    // per op: kappa on the extended grid
   int* d_flag = nullptr;            // device error flag (singular pivot)
+  // plane-block (3D) solves: subdomains grouped by distinct operator
+  int ngrp = 0, grp_maxcnt = 0;
+  int* d_grp_op = nullptr;          // [ngrp] operator of the group
+  int* d_grp_off = nullptr;         // [ngrp] first entry in d_grp_ids
+  int* d_grp_cnt = nullptr;         // [ngrp] subdomains in the group
+  int* d_grp_ids = nullptr;         // [nsub] subdomain ids, grouped
+  int* d_zero_int = nullptr;        // {0}
+  int* d_one_int = nullptr;         // {1}
+  int* d_piv = nullptr;             // [nops][n] Gauss-Jordan row interchanges
 
   // precision-dependent factors: element type cpx<float> or cpx<double>
   void* d_X = nullptr;              // [nops][K][nP][nP] column-major blocks
+                                    // (3D: [nops][K][n][n], no padding)
   void* d_T = nullptr;              // [nops][NI][NI] column-major (2D)
   void* d_coefT = nullptr;          // coefficients in working precision
   void* d_cface = nullptr;          // [nops][NI/2] face coupling per face and t
@@ -240,6 +250,8 @@ template <class T>
 hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C);
 template <class T>
 hipError_t launch_face_coef(hdsw_ctx* c);
+template <class T>
+hipError_t launch_big_factor(hdsw_ctx* c, void* rbuf);
 hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C);
 hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r,
                            int C);

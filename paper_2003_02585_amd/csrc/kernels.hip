@@ -22,42 +22,76 @@
 namespace hdsw {
 
 // ------------------------------------------------------------ helpers
-__device__ inline int iface_dof_x(const GeoDev& g, int p, int k) {
-  // x-side interface dof of local node (p, k) in 2D, -1 if none
-  int W = g.W, na = g.na[0];
-  int s = -1, L = 0;
-  if (p == W) { s = 0; L = 0; }
-  else if (p == W - 1) { s = 0; L = 1; }
-  else if (p == W + na - 1) { s = 1; L = 0; }
-  else if (p == W + na) { s = 1; L = 1; }
-  if (s < 0) return -1;
-  return g.side_off[s] + L * g.side_len[s] + k;
+// Local node coordinates loc[3] (x, y, z) of an extended subdomain; a block
+// is a grid line in 2D (in-block index p = x, block k = y) and a plane in
+// 3D (p = y n_x + x, k = z).
+__device__ inline void block_node(const GeoDev& g, int p, int k, int loc[3]) {
+  if (g.dim == 2) {
+    loc[0] = p;
+    loc[1] = k;
+    loc[2] = 0;
+  } else {
+    loc[1] = p / g.ne[0];
+    loc[0] = p - loc[1] * g.ne[0];
+    loc[2] = k;
+  }
 }
-__device__ inline int iface_dof_y(const GeoDev& g, int p, int k) {
-  int W = g.W, na = g.na[1];
-  int s = -1, L = 0;
-  if (k == W) { s = 2; L = 0; }
-  else if (k == W - 1) { s = 2; L = 1; }
-  else if (k == W + na - 1) { s = 3; L = 0; }
-  else if (k == W + na) { s = 3; L = 1; }
-  if (s < 0) return -1;
-  return g.side_off[s] + L * g.side_len[s] + p;
+__device__ inline void sub_coords(const GeoDev& g, int s, int sc[3]) {
+  sc[0] = s % g.P[0];
+  sc[1] = (s / g.P[0]) % g.P[1];
+  sc[2] = s / (g.P[0] * g.P[1]);
 }
-// local node (p, k) of interface dof i (2D)
-__device__ inline void dof_node2d(const GeoDev& g, int i, int& p, int& k) {
-  int s = 0;
-  while (s < 3 && i >= g.side_off[s + 1]) ++s;
-  int r = i - g.side_off[s];
-  int L = r / g.side_len[s];
-  int t = r - L * g.side_len[s];
-  int axis = s >> 1;
-  int na = g.na[axis];
-  int layer = (s & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
-  if (axis == 0) { p = layer; k = t; }
-  else { p = t; k = layer; }
+// tangential index of a node on a face normal to `axis`: the other axes in
+// increasing order, the first one fastest
+__device__ inline int face_t(const GeoDev& g, int axis, const int loc[3]) {
+  if (g.dim == 2) return loc[1 - axis];
+  const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+  return loc[a2] * g.ne[a1] + loc[a1];
+}
+// interface dof of a local node on the faces normal to `axis`, -1 if none
+// (layer 0: the subdomain's boundary layer, layer 1: the next one out)
+__device__ inline int iface_dof(const GeoDev& g, int axis, const int loc[3]) {
+  const int W = g.W, na = g.na[axis], pa = loc[axis];
+  int s = -1, L = 0;
+  if (pa == W) { s = 0; L = 0; }
+  else if (pa == W - 1) { s = 0; L = 1; }
+  else if (pa == W + na - 1) { s = 1; L = 0; }
+  else if (pa == W + na) { s = 1; L = 1; }
+  if (s < 0) return -1;
+  const int f = 2 * axis + s;
+  return g.side_off[f] + L * g.side_len[f] + face_t(g, axis, loc);
+}
+// local node of interface dof i
+__device__ inline void dof_node(const GeoDev& g, int i, int loc[3]) {
+  int f = 0;
+  while (f < 2 * g.dim - 1 && i >= g.side_off[f + 1]) ++f;
+  const int r = i - g.side_off[f];
+  const int L = r / g.side_len[f];
+  const int t = r - L * g.side_len[f];
+  const int axis = f >> 1, na = g.na[axis];
+  loc[axis] = (f & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
+  if (g.dim == 2) {
+    loc[1 - axis] = t;
+    loc[2] = 0;
+  } else {
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    loc[a2] = t / g.ne[a1];
+    loc[a1] = t - loc[a2] * g.ne[a1];
+  }
 }
 __device__ inline bool owned_axis(const GeoDev& g, int a, int bc, int loc) {
   return (loc >= g.W || bc == 0) && (loc < g.W + g.na[a] || bc == g.P[a] - 1);
+}
+// global node index of a subdomain-local node, -1 if the subdomain does not
+// own it
+__device__ inline long long owned_global(const GeoDev& g, const int sc[3], const int loc[3]) {
+  long long G = 0, stride = 1;
+  for (int a = 0; a < g.dim; ++a) {
+    if (!owned_axis(g, a, sc[a], loc[a])) return -1;
+    G += (long long)(sc[a] * g.na[a] + loc[a]) * stride;
+    stride *= g.M[a];
+  }
+  return G;
 }
 
 // ------------------------------------------------------------ assembly
@@ -102,8 +136,74 @@ __global__ void k_assemble2d(c128* coef, size_t stride, const c128* al, int o_nx
   }
 }
 
+// 3D: ax[n_z][n_y][n_x + 1], ay[n_z][n_y + 1][n_x], az[n_z + 1][n_y][n_x],
+// dg[n_z][n_y][n_x]; a^x = alpha_y alpha_z / alpha_x(half), and so on
+// (eq. (PML3)), dg = h^2 k^2 J - (sum of the six face coefficients).
+struct AlphaOff {
+  int o[6];
+};
+__global__ void k_assemble3d(c128* coef, size_t stride, const c128* al, AlphaOff ao,
+                             const double* kap, GeoDev g, double h2, int nops) {
+  const int* o = ao.o;
+  const int op = blockIdx.y;
+  if (op >= nops) return;
+  const int nx = g.ne[0], ny = g.ne[1], nz = g.ne[2];
+  const int onx = o[0], ohx = o[1], ony = o[2], ohy = o[3], onz = o[4], ohz = o[5];
+  c128* ax = coef + (size_t)op * stride;
+  c128* ay = ax + (size_t)nz * ny * (nx + 1);
+  c128* az = ay + (size_t)nz * (ny + 1) * nx;
+  c128* dg = az + (size_t)(nz + 1) * ny * nx;
+  const double* kp = kap + (size_t)op * nx * ny * nz;
+  const long long t1 = (long long)nz * ny * (nx + 1), t2 = (long long)nz * (ny + 1) * nx,
+                  t3 = (long long)(nz + 1) * ny * nx, t4 = (long long)nz * ny * nx;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       idx < t1 + t2 + t3 + t4; idx += (long long)gridDim.x * blockDim.x) {
+    long long r = idx;
+    if (r < t1) {
+      int q = (int)(r % (nx + 1)), y = (int)((r / (nx + 1)) % ny), z = (int)(r / ((nx + 1) * (long long)ny));
+      ax[r] = al[ony + y] * al[onz + z] * cinv(al[ohx + q]);
+      continue;
+    }
+    r -= t1;
+    if (r < t2) {
+      int x = (int)(r % nx), q = (int)((r / nx) % (ny + 1)), z = (int)(r / (nx * (long long)(ny + 1)));
+      ay[r] = al[onx + x] * al[onz + z] * cinv(al[ohy + q]);
+      continue;
+    }
+    r -= t2;
+    if (r < t3) {
+      int x = (int)(r % nx), y = (int)((r / nx) % ny), q = (int)(r / (nx * (long long)ny));
+      az[r] = al[onx + x] * al[ony + y] * cinv(al[ohz + q]);
+      continue;
+    }
+    r -= t3;
+    int x = (int)(r % nx), y = (int)((r / nx) % ny), z = (int)(r / (nx * (long long)ny));
+    c128 axl = al[ony + y] * al[onz + z] * cinv(al[ohx + x]);
+    c128 axr = al[ony + y] * al[onz + z] * cinv(al[ohx + x + 1]);
+    c128 ayl = al[onx + x] * al[onz + z] * cinv(al[ohy + y]);
+    c128 ayr = al[onx + x] * al[onz + z] * cinv(al[ohy + y + 1]);
+    c128 azl = al[onx + x] * al[ony + y] * cinv(al[ohz + z]);
+    c128 azr = al[onx + x] * al[ony + y] * cinv(al[ohz + z + 1]);
+    double kk = kp[r];
+    c128 J = al[onx + x] * al[ony + y] * al[onz + z];
+    c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
+    dg[r] = d - axl - axr - ayl - ayr - azl - azr;
+  }
+}
+
 hipError_t launch_assemble(hdsw_ctx* c) {
   const Geometry& g = c->g;
+  if (g.dim == 3) {
+    long long tot = (long long)g.ne[2] * g.ne[1] * (g.ne[0] + 1) +
+                    (long long)g.ne[2] * (g.ne[1] + 1) * g.ne[0] +
+                    (long long)(g.ne[2] + 1) * g.ne[1] * g.ne[0] + g.sub_nodes;
+    dim3 grid((unsigned)std::min<long long>((tot + 255) / 256, 1 << 16), c->nops);
+    AlphaOff ao;
+    for (int i = 0; i < 6; ++i) ao.o[i] = c->alpha_sub_off[i];
+    hipLaunchKernelGGL(k_assemble3d, grid, dim3(256), 0, c->stream, c->d_coef, c->coef_stride,
+                       c->d_alpha_sub, ao, c->d_kappa_sub, c->gd, g.h * g.h, c->nops);
+    return hipGetLastError();
+  }
   int tot = g.K * (g.n + 1) + (g.K + 1) * g.n;
   dim3 grid((tot + 255) / 256, c->nops);
   hipLaunchKernelGGL(k_assemble2d, grid, dim3(256), 0, c->stream, c->d_coef,
@@ -151,21 +251,24 @@ __global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch
     int rem = (int)(r - (long long)k * C * n);
     int col = rem / n, p = rem - col * n;
     cpx<T> v = mk<T>(T(0), T(0));
+    int loc[3];
+    block_node(g, p, k, loc);
     if (mode == 2) {
       int d = col0 + col;
-      if (iface_dof_x(g, p, k) == d || iface_dof_y(g, p, k) == d) v.re = T(1);
+      for (int a = 0; a < g.dim; ++a)
+        if (iface_dof(g, a, loc) == d) v.re = T(1);
     } else {
       int s = ids[b];
-      int bx = s % g.P[0], by = s / g.P[0];
-      if (owned_axis(g, 0, bx, p) && owned_axis(g, 1, by, k)) {
-        long long G = (long long)(by * g.na[1] + k) * g.M[0] + (bx * g.na[0] + p);
-        v = ccast<T>(rg[(long long)col * glob + G]);
-      }
+      int sc[3];
+      sub_coords(g, s, sc);
+      long long G = owned_global(g, sc, loc);
+      if (G >= 0) v = ccast<T>(rg[(long long)col * glob + G]);
       if (mode == 1) {
         const cpx<T>* a = accg + ((long long)s * C + col) * g.NI;
-        int dx = iface_dof_x(g, p, k), dy = iface_dof_y(g, p, k);
-        if (dx >= 0) v = v + a[dx];
-        if (dy >= 0) v = v + a[dy];
+        for (int ax = 0; ax < g.dim; ++ax) {
+          int d = iface_dof(g, ax, loc);
+          if (d >= 0) v = v + a[d];
+        }
       }
     }
     *dst = v;
@@ -196,8 +299,10 @@ __global__ void k_extract_iface(const cpx<T>* panel, int nbatch, int C, cpx<T>* 
     int b = (int)(idx / ((long long)C * g.NI));
     int r = (int)(idx - (long long)b * C * g.NI);
     int col = r / g.NI, i = r - col * g.NI;
-    int p, k;
-    dof_node2d(g, i, p, k);
+    int loc[3];
+    dof_node(g, i, loc);
+    const int p = g.dim == 2 ? loc[0] : loc[1] * g.ne[0] + loc[0];
+    const int k = loc[g.dim - 1];
     dst[b * dst_sb + (long long)col * dst_ld + i] =
         panel[(((long long)b * (g.K + 1) + k) * C + col) * g.n + p];
   }
@@ -228,9 +333,11 @@ __global__ void k_write_owned(const cpx<T>* panel, int C, c128* glob, long long 
     int k = (int)(r / ((long long)C * n));
     int rem = (int)(r - (long long)k * C * n);
     int col = rem / n, p = rem - col * n;
-    int bx = s % g.P[0], by = s / g.P[0];
-    if (!(owned_axis(g, 0, bx, p) && owned_axis(g, 1, by, k))) continue;
-    long long G = (long long)(by * g.na[1] + k) * g.M[0] + (bx * g.na[0] + p);
+    int sc[3], loc[3];
+    sub_coords(g, s, sc);
+    block_node(g, p, k, loc);
+    long long G = owned_global(g, sc, loc);
+    if (G < 0) continue;
     c128 v = ccast<double>(panel[(long long)s * (K + 1) * C * n + r]);
     c128* dst = glob + (long long)col * gn + G;
     *dst = accumulate ? (*dst + v) : v;
@@ -255,11 +362,20 @@ __global__ void k_rhs_from_f(const c128* f, c128* b, int C, GeoDev g, double h2,
        idx += (long long)gridDim.x * blockDim.x) {
     int col = (int)(idx / gn);
     long long G = idx - col * gn;
-    int gy = (int)(G / g.M[0]), gx = (int)(G - (long long)gy * g.M[0]);
-    int ix = gx - g.W, iy = gy - g.W;
+    long long I = 0, istride = 1, ni = 1;
+    bool inside = true;
+    for (int a = 0; a < g.dim; ++a) {
+      int ga = (int)(G % g.M[a]);
+      G /= g.M[a];
+      int ia = ga - g.W;
+      inside = inside && ia >= 0 && ia < g.N[a];
+      I += (long long)ia * istride;
+      istride *= g.N[a];
+      ni *= g.N[a];
+    }
     c128 v = mk<double>(0.0, 0.0);
-    if (ix >= 0 && ix < g.N[0] && iy >= 0 && iy < g.N[1]) {
-      c128 fv = f[(long long)col * g.N[0] * g.N[1] + (long long)iy * g.N[0] + ix];
+    if (inside) {
+      c128 fv = f[(long long)col * ni + I];
       v = mk<double>(h2 * fv.re, h2 * fv.im);
     }
     b[idx] = v;
@@ -305,9 +421,61 @@ __global__ void k_residual2d(const c128* b, const c128* x, c128* r, int C,
     r[idx] = b ? (b[idx] - su) : su;
   }
 }
+// 3D: 7-point operator of eq. (PML3) on the global grid
+__global__ void k_residual3d(const c128* b, const c128* x, c128* r, int C, const c128* al,
+                             AlphaOff ao, const double* kap, GeoDev g, double h2,
+                             long long gn) {
+  const int* o = ao.o;
+  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
+  const long long Mxy = (long long)Mx * My;
+  const int onx = o[0], ohx = o[1], ony = o[2], ohy = o[3], onz = o[4], ohz = o[5];
+  long long tot = (long long)C * gn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int col = (int)(idx / gn);
+    long long G = idx - col * gn;
+    int gz = (int)(G / Mxy);
+    long long rem = G - gz * Mxy;
+    int gy = (int)(rem / Mx), gx = (int)(rem - (long long)gy * Mx);
+    const c128* xc = x + (long long)col * gn;
+    c128 u = xc[G];
+    c128 anx = al[onx + gx], any = al[ony + gy], anz = al[onz + gz];
+    c128 axl = any * anz * cinv(al[ohx + gx]);
+    c128 axr = any * anz * cinv(al[ohx + gx + 1]);
+    c128 ayl = anx * anz * cinv(al[ohy + gy]);
+    c128 ayr = anx * anz * cinv(al[ohy + gy + 1]);
+    c128 azl = anx * any * cinv(al[ohz + gz]);
+    c128 azr = anx * any * cinv(al[ohz + gz + 1]);
+    int ix = min(max(gx - g.W, 0), g.N[0] - 1);
+    int iy = min(max(gy - g.W, 0), g.N[1] - 1);
+    int iz = min(max(gz - g.W, 0), g.N[2] - 1);
+    double kk = kap[((long long)iz * g.N[1] + iy) * g.N[0] + ix];
+    c128 J = anx * any * anz;
+    c128 su = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im) * u;
+    c128 z = mk<double>(0.0, 0.0);
+    c128 ul = gx > 0 ? xc[G - 1] : z;
+    c128 ur = gx < Mx - 1 ? xc[G + 1] : z;
+    c128 ud = gy > 0 ? xc[G - Mx] : z;
+    c128 uu = gy < My - 1 ? xc[G + Mx] : z;
+    c128 ub = gz > 0 ? xc[G - Mxy] : z;
+    c128 uf = gz < Mz - 1 ? xc[G + Mxy] : z;
+    su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud) +
+         azr * (uf - u) - azl * (u - ub);
+    r[idx] = b ? (b[idx] - su) : su;
+  }
+}
+
 hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, int C) {
   long long tot = (long long)C * c->g.glob_nodes;
   int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  if (c->g.dim == 3) {
+    AlphaOff ao;
+    for (int i = 0; i < 6; ++i) ao.o[i] = c->alpha_glob_off[i];
+    hipLaunchKernelGGL(k_residual3d, dim3(blocks), dim3(256), 0, c->stream, b, x, r, C,
+                       c->d_alpha_glob, ao, c->d_kappa, c->gd, c->g.h * c->g.h,
+                       c->g.glob_nodes);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_residual2d, dim3(blocks), dim3(256), 0, c->stream, b, x, r, C,
                      c->d_alpha_glob, c->alpha_glob_off[0], c->alpha_glob_off[1],
                      c->alpha_glob_off[2], c->alpha_glob_off[3], c->d_kappa, c->gd,
@@ -359,14 +527,21 @@ hipError_t launch_norms(hdsw_ctx* c, const c128* v, int C, double* d_out) {
 
 __global__ void k_extract_interior(const c128* glob, c128* out, int C, GeoDev g,
                                    long long gn) {
-  long long ni = (long long)g.N[0] * g.N[1];
+  long long ni = 1;
+  for (int a = 0; a < g.dim; ++a) ni *= g.N[a];
   long long tot = (long long)C * ni;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
        idx += (long long)gridDim.x * blockDim.x) {
     int col = (int)(idx / ni);
     long long r = idx - col * ni;
-    int iy = (int)(r / g.N[0]), ix = (int)(r - (long long)iy * g.N[0]);
-    out[idx] = glob[(long long)col * gn + (long long)(iy + g.W) * g.M[0] + ix + g.W];
+    long long G = 0, stride = 1;
+    for (int a = 0; a < g.dim; ++a) {
+      int ia = (int)(r % g.N[a]);
+      r /= g.N[a];
+      G += (long long)(ia + g.W) * stride;
+      stride *= g.M[a];
+    }
+    out[idx] = glob[(long long)col * gn + G];
   }
 }
 hipError_t launch_extract_interior(hdsw_ctx* c, const c128* glob, c128* out, int C) {

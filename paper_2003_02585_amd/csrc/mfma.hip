@@ -23,29 +23,9 @@
 //   [Yr | Yi] = Xr [Vr | Vi] + Xi [-Vi | Vr],
 // two real 16x16x4 MFMAs per 16-row tile and 4-deep slice of the sum.
 #include "hdsw_internal.hpp"
+#include "mfma_ops.hpp"
 
 namespace hdsw {
-
-template <class T>
-struct MF;
-template <>
-struct MF<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mfma(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  // accumulator register i of lane l holds row 4 (l / 16) + i, column l % 16
-  static __device__ inline int row(int l, int i) { return 4 * (l >> 4) + i; }
-};
-template <>
-struct MF<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mfma(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // accumulator register i of lane l holds row l / 16 + 4 i, column l % 16
-  static __device__ inline int row(int l, int i) { return (l >> 4) + 4 * i; }
-};
 
 // ------------------------------------------------------------ matvec
 // yb[r][c] = sum_j Xb(r, j) vb[j][c] for 8 columns c (LDS, row-major with the
@@ -403,7 +383,23 @@ static hipError_t launch_solve_nw(hdsw_ctx* c, int nbatch, const int* d_ops, int
 }
 
 template <class T>
+hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int* grp_op,
+                            const int* grp_off, const int* grp_cnt, const int* ids,
+                            int ngroups, int maxcnt, int C);
+
+template <class T>
 hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
+  if (c->g.dim == 3) {
+    // plane blocks: one GEMM per plane and operator group; the batch is
+    // either every subdomain (grouped by operator) or one operator's panel
+    if (nbatch == c->g.nsub && d_ops == c->d_op_of_sub)
+      return launch_big_solve<T>(c, nbatch, d_ops, c->d_grp_op, c->d_grp_off, c->d_grp_cnt,
+                                 c->d_grp_ids, c->ngrp, c->grp_maxcnt, C);
+    if (nbatch == 1)
+      return launch_big_solve<T>(c, 1, d_ops, d_ops, c->d_zero_int, c->d_one_int,
+                                 c->d_zero_int, 1, 1, C);
+    return hipErrorInvalidValue;
+  }
   const int nw = solve_nw<T>(c->g.nP);
   if (nw == 8) return launch_solve_nw<T, 8>(c, nbatch, d_ops, C);
   if (nw == 4) return launch_solve_nw<T, 4>(c, nbatch, d_ops, C);
@@ -580,9 +576,9 @@ hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle) {
 // two 8-column MFMA tiles over the whole sum.
 struct FaceSet {
   int n;                 // active faces
-  int face[4];           // face ids (0:-x, 1:+x, 2:-y, 3:+y)
-  int start[4];          // first row (or sum index) of the face
-  int lq[4];             // destination sweep per face (outputs only)
+  int face[6];           // face ids (0:-x, 1:+x, 2:-y, 3:+y, 4:-z, 5:+z)
+  int start[6];          // first row (or sum index) of the face
+  int lq[6];             // destination sweep per face (outputs only)
 };
 __device__ inline int fs_find(const FaceSet& fs, int idx) {
   int q = 0;
@@ -648,11 +644,11 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
   int rq = orow - fout.start[q];
   int lay = rq / len, t = rq - lay * len;
   int d = g.side_off[f] + rq;
-  int scc[2] = {s % g.P[0], s / g.P[0]};
+  int scc[3] = {s % g.P[0], (s / g.P[0]) % g.P[1], s / (g.P[0] * g.P[1])};
   int axis = f >> 1;
   scc[axis] += (f & 1) ? 1 : -1;
   if (scc[axis] < 0 || scc[axis] >= g.P[axis]) return o;
-  int recv = scc[0] + g.P[0] * scc[1];
+  int recv = scc[0] + g.P[0] * (scc[1] + g.P[1] * scc[2]);
   int fo = f ^ 1;
   size_t rb = (size_t)lq * slot_stride + ((size_t)recv * C + col) * NI;
   if (add_y) o.yo = (long long)(((size_t)s * C + col) * NI + d);
@@ -838,12 +834,30 @@ __global__ void k_face_coef(cpx<T>* cface, const cpx<T>* coefT, size_t cstride, 
        idx += gridDim.x * blockDim.x) {
     int op = idx / half, i = idx - op * half;
     int f = 0;
-    while (f < 3 && i >= g.side_off[f + 1] / 2) ++f;
+    while (f < 2 * g.dim - 1 && i >= g.side_off[f + 1] / 2) ++f;
     int t = i - g.side_off[f] / 2;
     const cpx<T>* co = coefT + (size_t)op * cstride;
+    const int axis = f >> 1;
+    // half-point index across the face, between layer 0 and layer 1
+    const int q = (f & 1) ? g.W + g.na[axis] : g.W;
     cpx<T> v;
-    if (f < 2) v = co[(size_t)t * (g.n + 1) + (f == 0 ? g.W : g.W + g.na[0])];
-    else v = co[(size_t)g.K * (g.n + 1) + (size_t)(f == 2 ? g.W : g.W + g.na[1]) * g.n + t];
+    if (g.dim == 2) {
+      if (f < 2) v = co[(size_t)t * (g.n + 1) + q];
+      else v = co[(size_t)g.K * (g.n + 1) + (size_t)q * g.n + t];
+    } else {
+      // faces: x t = z n_y + y, y t = z n_x + x, z t = y n_x + x
+      const int nx = g.ne[0], ny = g.ne[1], nz = g.ne[2];
+      const size_t o_ay = (size_t)nz * ny * (nx + 1);
+      const size_t o_az = o_ay + (size_t)nz * (ny + 1) * nx;
+      if (axis == 0) {
+        v = co[(size_t)t * (nx + 1) + q];
+      } else if (axis == 1) {
+        int z = t / nx, x = t - z * nx;
+        v = co[o_ay + ((size_t)z * (ny + 1) + q) * nx + x];
+      } else {
+        v = co[o_az + (size_t)q * ny * nx + t];
+      }
+    }
     cface[idx] = v;
   }
 }

@@ -316,3 +316,70 @@ def test_layer2d_full_size_against_sampled_global_solution(H, rounds, gm):
          f"iterations {sorted(set(i for i, _ in info))}")
     assert e < 1e-8
     assert en < 1e-8
+
+
+# ---------------------------------------------------------------- 3D
+# Algorithm 4.1 with plane blocks (n = n_x n_y) on the dense-block path.
+# Tiny subdomains need a weaker layer (pml_R 1e-4, as in the oracle's own
+# 3D pins).
+def _case3(Ns, W, P, layer=None, nrhs=2, seed=7, ppw=6):
+    h = 1.0 / Ns[0]
+    k = 2 * np.pi / (ppw * h)
+    kap = wl.constant_kappa(Ns, k) if layer is None else \
+        wl.two_layer_kappa(Ns, h, k, layer * k, 0.37)
+    pos = wl.random_positions(nrhs, 3, seed, 0.2, 0.8)
+    f = wl.sources(Ns, h, pos, 2 * h)
+    prob = O.Problem(kap, h, W, pml_R=1e-4)
+    part = O.Partition(prob, P)
+    b = np.stack([O.global_rhs(prob, fi) for fi in f])
+    return dict(h=h, kap=kap, f=f, prob=prob, part=part, b=b, P=P, W=W)
+
+
+DDM3_CASES = [
+    ((12, 12, 12), 3, (2, 2, 2), None, 1),     # n = 144, K = 12
+    ((18, 18, 18), 3, (3, 3, 3), None, 1),     # 27 subdomains, as the 96^3 workload
+    ((16, 24, 16), 4, (2, 3, 2), 1.5, 2),      # unequal axes, two layers, two rounds
+]
+
+
+@pytest.mark.parametrize("Ns,W,P,layer,rounds", DDM3_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_3d_ddm_matches_oracle(H, Ns, W, P, layer, rounds, prec):
+    c = _case3(Ns, W, P, layer)
+    sol = O.SubdomainSolvers(c["part"])
+    ref = [O.ddm_apply(c["prob"], c["part"], bi, rounds=rounds, solvers=sol) for bi in c["b"]]
+    _say(f"3d ddm {prec} N={Ns} W={W} P={P} layer={layer} rounds={rounds}")
+    p = H.HDSW_FP64 if prec == "fp64" else H.HDSW_MIXED
+    ctx = _ctx(H, dict(kap=c["kap"], h=c["h"], P=P, W=W), precision=p, rounds=rounds,
+               pml_R=1e-4)
+    try:
+        r = torch.from_numpy(c["b"]).cuda()
+        z = torch.zeros_like(r)
+        H.hdsw_apply_precond(ctx, r, z, r.shape[0])
+        got = z.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    e = _rel(got, ref)
+    _say(f"  rel diff {e:.3e}")
+    assert e < (1e-10 if prec == "fp64" else 2e-4)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_3d_solve_reaches_global_solution(H, prec):
+    c = _case3((18, 18, 18), 3, (3, 3, 3), None, nrhs=2, seed=11)
+    ug = O.solve_global(c["prob"], c["b"], method="sparse")
+    sl = c["prob"].interior_slice()
+    _say(f"3d solve {prec}")
+    p = H.HDSW_FP64 if prec == "fp64" else H.HDSW_MIXED
+    ctx = _ctx(H, dict(kap=c["kap"], h=c["h"], P=c["P"], W=c["W"]), precision=p,
+               pml_R=1e-4, gmres_m=20, tol=1e-11, max_iter=60)
+    try:
+        ft = torch.from_numpy(c["f"]).cuda()
+        xt = torch.zeros_like(ft)
+        info, _ = H.hdsw_solve(ctx, ft, xt, ft.shape[0])
+        x = xt.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    e = _rel(x, [u[sl] for u in ug])
+    _say(f"  rel err {e:.3e}, iterations {[i for i, _ in info]}")
+    assert e < 1e-8
