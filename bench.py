@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--gmres-m", type=int, default=0, help="GMRES(m) instead of refinement")
     ap.add_argument("--rounds", type=int, default=None, help="rounds of sweeps per DDM")
     ap.add_argument("--hbm-budget-gb", type=float, default=0.0)
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 comparison path (factors too large for both)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (HBM counter scale)")
     return ap.parse_args()
@@ -62,10 +64,13 @@ def run_path(H, torch, w, precision, steps, warmup, tol, timing, a):
     ctx = H.hdsw_setup(w["kappa"], w["h"], w["P"], w["W"], opt, stream=stream)
     try:
         torch.cuda.synchronize()
+        H.hdsw_timing_enable(ctx, True)
         t0 = time.perf_counter()
         H.hdsw_factor(ctx)
         torch.cuda.synchronize()
         t_factor = time.perf_counter() - t0
+        kt_factor = H.hdsw_timing_get(ctx, 2)
+        H.hdsw_timing_enable(ctx, False)
         f = torch.from_numpy(w["f"]).cuda()
         x = torch.zeros_like(f)
         nrhs = f.shape[0]
@@ -92,7 +97,7 @@ def run_path(H, torch, w, precision, steps, warmup, tol, timing, a):
             H.hdsw_timing_enable(ctx, False)
         fb, nops, ws = H.hdsw_query(ctx)
         return dict(total=total, lat=lat, info=info, x=x.cpu().numpy(), t_factor=t_factor,
-                    kt=kt, factor_bytes=fb, nops=nops, ws=ws, nrhs=nrhs)
+                    kt=kt, factor_bytes=fb, nops=nops, ws=ws, nrhs=nrhs, kt_factor=kt_factor)
     finally:
         H.hdsw_destroy(ctx)
 
@@ -124,6 +129,22 @@ def cpu_baseline(w, iters, nsample):
                 sample=(f"{nsample} RHS x 1 DDM application (+ residual) of the same "
                         f"workload, {t_app:.2f} s each, scaled by the {iters} iterations "
                         f"the FP64 path needed; factorization {t_fac:.2f} s not counted"))
+
+
+def factor_mfma(mixed, fp64):
+    """Achieved rate of the factorization (8 n^3 flops per block and
+    distinct operator) against the MFMA peak of its precision."""
+    out = {}
+    for name, r, peak in (("mixed", mixed, PEAK[("mfma", "f32")]),
+                          ("fp64", fp64, PEAK[("mfma", "f64")])):
+        if r is None:
+            continue
+        ms, n, fl, _ = r["kt_factor"]
+        if n and ms > 0:
+            ach = fl / (ms * 1e-3) / 1e12
+            out[name] = {"ms": round(ms, 3), "achieved_TFLOPs": round(ach, 3),
+                         "peak": peak, "frac": round(ach / peak, 4)}
+    return out
 
 
 def describe(a, w, nrhs):
@@ -189,18 +210,24 @@ def main():
         w["rounds"] = a.rounds
     mixed = run_path(H, torch, w, H.HDSW_MIXED, a.steps, a.warmup, a.tol, True, a)
     fsteps = a.fp64_steps if a.fp64_steps is not None else max(1, a.steps // 2)
-    fp64 = run_path(H, torch, w, H.HDSW_FP64, fsteps, 1, a.tol, False, a)
+    fp64 = None if a.no_fp64 else run_path(H, torch, w, H.HDSW_FP64, fsteps, 1, a.tol, False, a)
     nrhs = mixed["nrhs"]
     value = nrhs * a.steps / mixed["total"]
-    v64 = nrhs * fsteps / fp64["total"]
+    v64 = nrhs * fsteps / fp64["total"] if fp64 else None
     lat = np.array(mixed["lat"]) * 1e3
     # accuracy: mixed vs FP64 results (both iterated to the same tolerance)
-    x1, x2 = mixed["x"], fp64["x"]
-    rel_mf = max(np.linalg.norm(p - q) / np.linalg.norm(q) for p, q in zip(x1, x2))
+    rel_mf = None
+    if fp64:
+        x1, x2 = mixed["x"], fp64["x"]
+        rel_mf = max(np.linalg.norm(p - q) / np.linalg.norm(q) for p, q in zip(x1, x2))
     # roofline of the dominant kernel class, from live HIP events
     kt = mixed["kt"]
-    names = {0: "k_solve_fwd+k_solve_bwd (batched block solve)",
-             1: "k_sweep_step (fused sweep step)"}
+    if w["kappa"].ndim == 3:
+        names = {0: "k_plane_rhs+k_cgemm (plane-block solve of every subdomain)",
+                 1: "k_sweep_step (fused sweep step)"}
+    else:
+        names = {0: "k_solve_fwd+k_solve_bwd (batched block solve)",
+                 1: "k_sweep_step (fused sweep step)"}
     peak = PEAK[("mfma", "f32")]
     kernels = {}
     for k in (0, 1):
@@ -219,7 +246,7 @@ def main():
             "traffic": measured_traffic(a, dom),
             "kernel": names[dom], "avg_launch_ms": d["avg_launch_ms"],
             "launches": d["launches"]}
-    iters64 = max(i for i, _ in fp64["info"])
+    iters64 = max(i for i, _ in fp64["info"]) if fp64 else max(i for i, _ in mixed["info"])
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(w, iters64, a.cpu_sample_rhs)
@@ -234,12 +261,16 @@ def main():
                    "distinct_operators": mixed["nops"]},
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "fp64_value": round(v64, 3), "speedup_mixed_vs_fp64": round(value / v64, 3),
-        "iters_mixed": [i for i, _ in mixed["info"]], "iters_fp64": [i for i, _ in fp64["info"]],
+        "fp64_value": round(v64, 3) if v64 else None,
+        "speedup_mixed_vs_fp64": round(value / v64, 3) if v64 else None,
+        "iters_mixed": [i for i, _ in mixed["info"]],
+        "iters_fp64": [i for i, _ in fp64["info"]] if fp64 else None,
         "rel_residual_max": max(r for _, r in mixed["info"]),
         "rel_diff_mixed_vs_fp64": rel_mf,
-        "factor_s": {"mixed": round(mixed["t_factor"], 3), "fp64": round(fp64["t_factor"], 3)},
-        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu,
+        "factor_s": {"mixed": round(mixed["t_factor"], 3),
+                     "fp64": round(fp64["t_factor"], 3) if fp64 else None},
+        "roofline": roof, "kernels": kernels, "factor_mfma": factor_mfma(mixed, fp64),
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 

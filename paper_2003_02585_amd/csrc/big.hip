@@ -33,31 +33,28 @@ namespace hdsw {
 // (Re b, -Im b) and (Im b, Re b) in the two halves of a 16-wide operand, so
 // that Re(A) x first + Im(A) x second gives [Re(AB) | Im(AB)] for 8 complex
 // columns.
-struct GemmArgs {
-  int M, N, Kd;
-  const void* A;
-  long long lda, sAz;
-  const void* B;
-  long long ldb, sb, sBz;
-  void* C;
-  long long ldc, sc, sCz;
-  int cpb;
-  const int* ids;
-  const int* grp_op;
-  const int* grp_off;
-  const int* grp_cnt;
-  int neg;
-  int beta;
-};
+constexpr int GM = 64, GN = 32, GPAD = 80;
 
-constexpr int GM = 64, GN = 32, GK = 16, GPAD = 80;
+// column k of A: k itself, or the column given by the segment map
+__device__ __forceinline__ long long gemm_acol(const GemmArgs& a, int k) {
+  if (a.nseg == 0) return k;
+  int s = 0;
+#pragma unroll
+  for (int q = 1; q < 6; ++q)
+    if (q < a.nseg && k >= a.seg_k0[q]) s = q;
+  return (long long)a.seg_c0[s] + (k - a.seg_k0[s]);
+}
 
-template <class T>
+// BK-deep chunks of the sum, double-buffered in LDS (one barrier per
+// chunk): the next chunk's global loads are in flight while the current one
+// is multiplied.
+template <class T, int BK>
 __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
   typedef typename MF<T>::v4 v4;
-  __shared__ cpx<T> As[GK][GPAD];        // [k][row]
-  __shared__ cpx<T> Bp[GK][GPAD];        // [k][4 groups x 16 operand columns]
-  __shared__ cpx<T> Cs[GN][GM];          // [col][row] epilogue staging
+  constexpr int AL = BK / 4;                 // A elements per thread
+  constexpr int BL = BK / 8;                 // B elements per thread
+  __shared__ cpx<T> As[2][BK][GPAD];         // [buf][k][row]
+  __shared__ cpx<T> Bp[2][BK][GPAD];         // [buf][k][4 groups x 16 operand columns]
   const int z = blockIdx.z;
   const int ncols = a.grp_cnt ? a.grp_cnt[z] * a.cpb : a.N;
   const int col0 = blockIdx.y * GN;
@@ -69,10 +66,9 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
   const cpx<T>* B = reinterpret_cast<const cpx<T>*>(a.B) + (long long)z * a.sBz;
   cpx<T>* C = reinterpret_cast<cpx<T>*>(a.C) + (long long)z * a.sCz;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const cpx<T> zero = mk<T>(T(0), T(0));
 
-  // this thread's B column for loading: 2 consecutive k of column bc
-  const int bc = tid >> 3, bk = (tid & 7) * 2;
+  // B: column bc, k = bk .. bk + BL - 1
+  const int bc = tid >> 3, bk = (tid & 7) * BL;
   const cpx<T>* bcol = nullptr;
   {
     int j = col0 + bc;
@@ -82,35 +78,12 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
       bcol = B + (long long)eid * a.sb + (long long)jj * a.ldb;
     }
   }
-  // A rows: row ar, k = ak .. ak + 3
-  const int ar = tid & 63, ak = (tid >> 6) * 4;
+  // A: row ar, k = ak .. ak + AL - 1
+  const int ar = tid & 63, ak = (tid >> 6) * AL;
   const bool arow_ok = row0 + ar < a.M;
-  const cpx<T>* acol = A + row0 + ar;
+  const cpx<T>* acol = A + (arow_ok ? (a.arow ? a.arow[row0 + ar] : row0 + ar) : 0);
 
-  cpx<T> ra[4], rb[2];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int k = k0 + ak + u;
-      ra[u] = (arow_ok && k < a.Kd) ? acol[(long long)k * a.lda] : zero;
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      int k = k0 + bk + u;
-      rb[u] = (bcol && k < a.Kd) ? bcol[k] : zero;
-    }
-  };
-  auto lstore = [&]() {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) As[ak + u][ar] = ra[u];
-    const int g = bc >> 3, cc = bc & 7;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      Bp[bk + u][g * 16 + cc] = mk<T>(rb[u].re, -rb[u].im);
-      Bp[bk + u][g * 16 + cc + 8] = mk<T>(rb[u].im, rb[u].re);
-    }
-  };
-
+  cpx<T> ra[AL], rb[BL];
   v4 accR[4], accI[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
@@ -118,25 +91,59 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
     accI[g] = accR[g];
   }
   const int mr = wave * 16 + (lane & 15), mk4 = lane >> 4, mc = lane & 15;
-  gload(0);
-  for (int k0 = 0; k0 < a.Kd; k0 += GK) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (k0 + GK < a.Kd) gload(k0 + GK);
+  const int nch = (a.Kd + BK - 1) / BK;
+
+#define HDSW_GEMM_LOAD(k0)                                                       \
+  {                                                                              \
+    _Pragma("unroll") for (int u = 0; u < AL; ++u) {                             \
+      int k = (k0) + ak + u;                                                     \
+      ra[u].re = T(0);                                                           \
+      ra[u].im = T(0);                                                           \
+      if (arow_ok && k < a.Kd) ra[u] = acol[gemm_acol(a, k) * a.lda];            \
+    }                                                                            \
+    _Pragma("unroll") for (int u = 0; u < BL; ++u) {                             \
+      int k = (k0) + bk + u;                                                     \
+      rb[u].re = T(0);                                                           \
+      rb[u].im = T(0);                                                           \
+      if (bcol && k < a.Kd) rb[u] = bcol[k];                                     \
+    }                                                                            \
+  }
+#define HDSW_GEMM_STORE(buf)                                                     \
+  {                                                                              \
+    _Pragma("unroll") for (int u = 0; u < AL; ++u) As[buf][ak + u][ar] = ra[u];  \
+    const int g_ = bc >> 3, cc_ = bc & 7;                                        \
+    _Pragma("unroll") for (int u = 0; u < BL; ++u) {                             \
+      Bp[buf][bk + u][g_ * 16 + cc_] = mk<T>(rb[u].re, -rb[u].im);               \
+      Bp[buf][bk + u][g_ * 16 + cc_ + 8] = mk<T>(rb[u].im, rb[u].re);            \
+    }                                                                            \
+  }
+
+  HDSW_GEMM_LOAD(0);
+  HDSW_GEMM_STORE(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) HDSW_GEMM_LOAD((ch + 1) * BK);
 #pragma unroll
-    for (int ks = 0; ks < GK / 4; ++ks) {
-      const cpx<T> av = As[ks * 4 + mk4][mr];
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const cpx<T> av = As[buf][ks * 4 + mk4][mr];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const cpx<T> p = Bp[ks * 4 + mk4][g * 16 + mc];
+        const cpx<T> p = Bp[buf][ks * 4 + mk4][g * 16 + mc];
         accR[g] = MF<T>::mfma(av.re, p.re, accR[g]);
         accI[g] = MF<T>::mfma(av.im, p.im, accI[g]);
       }
     }
+    if (ch + 1 < nch) HDSW_GEMM_STORE(buf ^ 1);
+    __syncthreads();
   }
-  // stage [Re | Im] halves as complex columns
-  T* cs = reinterpret_cast<T*>(&Cs[0][0]);
+#undef HDSW_GEMM_LOAD
+#undef HDSW_GEMM_STORE
+
+  // stage [Re | Im] halves as complex columns (reusing the A buffers)
+  cpx<T>(*Cs)[GM] = reinterpret_cast<cpx<T>(*)[GM]>(&As[0][0][0]);
+  static_assert(sizeof(As) >= sizeof(cpx<T>) * GN * GM, "staging does not fit");
+  T* cs = reinterpret_cast<T*>(&As[0][0][0]);
   const int part = mc >> 3, cc = mc & 7;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
@@ -165,10 +172,11 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
 }
 
 template <class T>
-static hipError_t gemm(hipStream_t st, const GemmArgs& a, int maxcols, int ngroups) {
+hipError_t gemm(hipStream_t st, const GemmArgs& a, int maxcols, int ngroups) {
   if (a.M <= 0 || maxcols <= 0 || ngroups <= 0) return hipSuccess;
   dim3 grid((a.M + GM - 1) / GM, (maxcols + GN - 1) / GN, ngroups);
-  hipLaunchKernelGGL(k_cgemm<T>, grid, dim3(256), 0, st, a);
+  constexpr int BK = sizeof(T) == 4 ? 32 : 16;
+  hipLaunchKernelGGL((k_cgemm<T, BK>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -469,6 +477,7 @@ hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int
 }
 
 #define HDSW_INST3(T)                                                                      \
+  template hipError_t gemm<T>(hipStream_t, const GemmArgs&, int, int);                     \
   template hipError_t launch_big_factor<T>(hdsw_ctx*, void*);                              \
   template hipError_t launch_big_solve<T>(hdsw_ctx*, int, const int*, const int*,          \
                                           const int*, const int*, const int*, int, int, int);

@@ -469,6 +469,48 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
     c->grp_maxcnt = std::max(c->grp_maxcnt, grp_cnt.back());
   }
   c->ngrp = c->nops;
+  // 3D sweep steps: face maps per sweep and per-step operator groups
+  std::vector<int> fmap, sg_op, sg_off, sg_cnt, sg_ids;
+  if (g.dim == 3) {
+    const Schedule& sc = c->sch;
+    for (int L = 0; L < sc.nsweeps; ++L) {
+      c->map_out_off.push_back((int)fmap.size());
+      for (int f = 0; f < 2 * g.dim; ++f)
+        if (sc.lprime[L * 6 + f] >= 0)
+          for (int r = 0; r < 2 * g.side_len[f]; ++r) fmap.push_back(g.side_off[f] + r);
+      c->map_in_off.push_back((int)fmap.size());
+      for (int f = 0; f < 2 * g.dim; ++f)
+        if (sc.in_active[L * 6 + f])
+          for (int r = 0; r < 2 * g.side_len[f]; ++r) fmap.push_back(g.side_off[f] + r);
+      for (int st = 0; st < sc.nsteps; ++st) {
+        int off = sc.step_off[L * sc.nsteps + st], cnt = sc.step_cnt[L * sc.nsteps + st];
+        c->sg_first.push_back((int)sg_op.size());
+        int ng = 0, mx = 0;
+        for (int o = 0; o < c->nops; ++o) {
+          int first = (int)sg_ids.size();
+          for (int bi = 0; bi < cnt; ++bi)
+            if (c->op_of_sub[sc.step_subs[off + bi]] == o) sg_ids.push_back(bi);
+          int n_o = (int)sg_ids.size() - first;
+          if (n_o == 0) continue;
+          sg_op.push_back(o);
+          sg_off.push_back(first);
+          sg_cnt.push_back(n_o);
+          ++ng;
+          mx = std::max(mx, n_o);
+        }
+        c->sg_n.push_back(ng);
+        c->sg_maxcnt.push_back(mx);
+      }
+    }
+    if (fmap.empty()) fmap.push_back(0);
+    if (sg_op.empty()) { sg_op.push_back(0); sg_off.push_back(0); sg_cnt.push_back(0); }
+    if (sg_ids.empty()) sg_ids.push_back(0);
+    SALLOC(c->d_fmap, fmap.size() * sizeof(int));
+    SALLOC(c->d_sg_op, sg_op.size() * sizeof(int));
+    SALLOC(c->d_sg_off, sg_off.size() * sizeof(int));
+    SALLOC(c->d_sg_cnt, sg_cnt.size() * sizeof(int));
+    SALLOC(c->d_sg_ids, sg_ids.size() * sizeof(int));
+  }
   SALLOC(c->d_grp_op, c->ngrp * sizeof(int));
   SALLOC(c->d_grp_off, c->ngrp * sizeof(int));
   SALLOC(c->d_grp_cnt, c->ngrp * sizeof(int));
@@ -498,6 +540,13 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   up(c->d_grp_off, grp_off.data(), c->ngrp * sizeof(int));
   up(c->d_grp_cnt, grp_cnt.data(), c->ngrp * sizeof(int));
   up(c->d_grp_ids, grp_ids.data(), g.nsub * sizeof(int));
+  if (g.dim == 3) {
+    up(c->d_fmap, fmap.data(), fmap.size() * sizeof(int));
+    up(c->d_sg_op, sg_op.data(), sg_op.size() * sizeof(int));
+    up(c->d_sg_off, sg_off.data(), sg_off.size() * sizeof(int));
+    up(c->d_sg_cnt, sg_cnt.data(), sg_cnt.size() * sizeof(int));
+    up(c->d_sg_ids, sg_ids.data(), sg_ids.size() * sizeof(int));
+  }
   if (he != hipSuccess) return fail(HDSW_EDEVICE);
   c->part_blocks = 256;
   *out = c;
@@ -585,10 +634,10 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   if (C > c->Cmax) {
-    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_y,
+    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_y, c->d_out,
                     c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
     for (void* p : ptrs) dev_free(c, p);
-    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_y = nullptr;
+    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_y = c->d_out = nullptr;
     c->d_xg = c->d_rg = c->d_bg = nullptr;
     c->d_part = c->d_norm = nullptr;
     c->Cmax = 0;
@@ -606,6 +655,7 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) * g.NI * e);
     WALLOC(c->d_accg, iface);
     WALLOC(c->d_y, iface);
+    if (g.dim == 3) WALLOC(c->d_out, iface);
     WALLOC(c->d_xg, (size_t)C * g.glob_nodes * sizeof(c128));
     WALLOC(c->d_rg, (size_t)C * g.glob_nodes * sizeof(c128));
     WALLOC(c->d_bg, (size_t)C * g.glob_nodes * sizeof(c128));
@@ -670,7 +720,7 @@ static hdsw_status ddm_impl(hdsw_ctx* c, const c128* r, c128* out, int C, int ac
         double fl = 8.0 * nin * nout * C * cnt;
         double by = nin * nout * e * std::min(cnt, c->nops) + (nin + 2 * nout) * C * e * cnt;
         TimedScope ts(c, KT_GEMM, fl, by);
-        HCHK(launch_sweep_step<T>(c, L, off, cnt, C));
+        HCHK(launch_sweep_step<T>(c, L, st, off, cnt, C));
       }
     }
   }
@@ -698,7 +748,7 @@ static size_t max_cols(hdsw_ctx* c) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   size_t per_col = (size_t)g.nsub * (g.K + 1) * g.n * e +
-                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + 2) +
+                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 3 : 2)) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
   size_t used = c->alloc_bytes;

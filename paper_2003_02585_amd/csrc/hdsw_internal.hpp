@@ -185,6 +185,15 @@ struct hdsw_ctx {
   int* d_zero_int = nullptr;        // {0}
   int* d_one_int = nullptr;         // {1}
   int* d_piv = nullptr;             // [nops][n] Gauss-Jordan row interchanges
+  // plane-block (3D) sweep steps: T rows / columns of the active faces per
+  // sweep, and the subdomains of every step grouped by operator
+  int* d_fmap = nullptr;
+  std::vector<int> map_out_off, map_in_off;   // per sweep, into d_fmap
+  int* d_sg_op = nullptr;
+  int* d_sg_off = nullptr;
+  int* d_sg_cnt = nullptr;
+  int* d_sg_ids = nullptr;                     // step-local entry indices
+  std::vector<int> sg_first, sg_n, sg_maxcnt;  // per (sweep, step)
 
   // precision-dependent factors: element type cpx<float> or cpx<double>
   void* d_X = nullptr;              // [nops][K][nP][nP] column-major blocks
@@ -200,6 +209,7 @@ struct hdsw_ctx {
   void* d_g = nullptr;              // [nsub][Cp/8][NI][8] sources of a step
   void* d_accg = nullptr;           // [nsub][C][NI] accumulated sources
   void* d_y = nullptr;              // [nsub][C][NI] source-driven outputs
+  void* d_out = nullptr;            // [nsub][C][NI] step outputs (3D)
   hdsw::c128* d_xg = nullptr;       // [C][glob] iterate (FP64)
   hdsw::c128* d_rg = nullptr;       // [C][glob] residual (FP64)
   hdsw::c128* d_bg = nullptr;       // [C][glob] right-hand side (FP64)
@@ -229,6 +239,33 @@ namespace hdsw {
 // kernel classes for timing
 enum { KT_SOLVE = 0, KT_GEMM = 1, KT_FACTOR = 2, KT_RESID = 3 };
 
+// Complex GEMM on the matrix cores (big.hip):
+struct GemmArgs {
+  int M, N, Kd;
+  const void* A;
+  long long lda, sAz;
+  const void* B;
+  long long ldb, sb, sBz;
+  void* C;
+  long long ldc, sc, sCz;
+  int cpb;
+  const int* ids;
+  const int* grp_op;
+  const int* grp_off;
+  const int* grp_cnt;
+  int neg;
+  int beta;
+  const int* arow;   // row r of A is row arow[r] of the stored matrix (nullable)
+  // column k of A: seg_c0[s] + (k - seg_k0[s]) for the segment s holding k
+  // (seg_k0 increasing, seg_k0[0] = 0), or k itself when nseg = 0
+  int nseg;
+  int seg_k0[6];
+  int seg_c0[6];
+};
+
+template <class T>
+hipError_t gemm(hipStream_t st, const GemmArgs& a, int maxcols, int ngroups);
+
 // ----- launchers (kernels.hip) ------------------------------------------
 hipError_t launch_assemble(hdsw_ctx* c);
 template <class T>
@@ -247,7 +284,7 @@ hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
 template <class T>
 hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate);
 template <class T>
-hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C);
+hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C);
 template <class T>
 hipError_t launch_face_coef(hdsw_ctx* c);
 template <class T>

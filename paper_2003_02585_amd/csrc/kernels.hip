@@ -22,36 +22,51 @@
 namespace hdsw {
 
 // ------------------------------------------------------------ helpers
-// Local node coordinates loc[3] (x, y, z) of an extended subdomain; a block
-// is a grid line in 2D (in-block index p = x, block k = y) and a plane in
-// 3D (p = y n_x + x, k = z).
-__device__ inline void block_node(const GeoDev& g, int p, int k, int loc[3]) {
-  if (g.dim == 2) {
-    loc[0] = p;
-    loc[1] = k;
-    loc[2] = 0;
-  } else {
-    loc[1] = p / g.ne[0];
-    loc[0] = p - loc[1] * g.ne[0];
-    loc[2] = k;
+// Local node coordinates (x, y, z) of an extended subdomain; a block is a
+// grid line in 2D (in-block index p = x, block k = y) and a plane in 3D
+// (p = y n_x + x, k = z).  Coordinates are kept in scalars: a small local
+// array indexed by a run-time axis would live in scratch memory.
+struct Loc {
+  int x, y, z;
+  __device__ int at(int a) const { return a == 0 ? x : (a == 1 ? y : z); }
+  __device__ void set(int a, int v) {
+    if (a == 0) x = v;
+    else if (a == 1) y = v;
+    else z = v;
   }
+};
+__device__ inline Loc block_node(const GeoDev& g, int p, int k) {
+  Loc l;
+  if (g.dim == 2) {
+    l.x = p;
+    l.y = k;
+    l.z = 0;
+  } else {
+    l.y = p / g.ne[0];
+    l.x = p - l.y * g.ne[0];
+    l.z = k;
+  }
+  return l;
 }
-__device__ inline void sub_coords(const GeoDev& g, int s, int sc[3]) {
-  sc[0] = s % g.P[0];
-  sc[1] = (s / g.P[0]) % g.P[1];
-  sc[2] = s / (g.P[0] * g.P[1]);
+__device__ inline Loc sub_coords(const GeoDev& g, int s) {
+  Loc c;
+  c.x = s % g.P[0];
+  c.y = (s / g.P[0]) % g.P[1];
+  c.z = s / (g.P[0] * g.P[1]);
+  return c;
 }
 // tangential index of a node on a face normal to `axis`: the other axes in
 // increasing order, the first one fastest
-__device__ inline int face_t(const GeoDev& g, int axis, const int loc[3]) {
-  if (g.dim == 2) return loc[1 - axis];
-  const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-  return loc[a2] * g.ne[a1] + loc[a1];
+__device__ inline int face_t(const GeoDev& g, int axis, const Loc& l) {
+  if (g.dim == 2) return axis == 0 ? l.y : l.x;
+  if (axis == 0) return l.z * g.ne[1] + l.y;
+  if (axis == 1) return l.z * g.ne[0] + l.x;
+  return l.y * g.ne[0] + l.x;
 }
 // interface dof of a local node on the faces normal to `axis`, -1 if none
 // (layer 0: the subdomain's boundary layer, layer 1: the next one out)
-__device__ inline int iface_dof(const GeoDev& g, int axis, const int loc[3]) {
-  const int W = g.W, na = g.na[axis], pa = loc[axis];
+__device__ inline int iface_dof(const GeoDev& g, int axis, const Loc& l) {
+  const int W = g.W, na = g.na[axis], pa = l.at(axis);
   int s = -1, L = 0;
   if (pa == W) { s = 0; L = 0; }
   else if (pa == W - 1) { s = 0; L = 1; }
@@ -59,37 +74,43 @@ __device__ inline int iface_dof(const GeoDev& g, int axis, const int loc[3]) {
   else if (pa == W + na) { s = 1; L = 1; }
   if (s < 0) return -1;
   const int f = 2 * axis + s;
-  return g.side_off[f] + L * g.side_len[f] + face_t(g, axis, loc);
+  return g.side_off[f] + L * g.side_len[f] + face_t(g, axis, l);
 }
 // local node of interface dof i
-__device__ inline void dof_node(const GeoDev& g, int i, int loc[3]) {
+__device__ inline Loc dof_node(const GeoDev& g, int i) {
   int f = 0;
   while (f < 2 * g.dim - 1 && i >= g.side_off[f + 1]) ++f;
   const int r = i - g.side_off[f];
   const int L = r / g.side_len[f];
   const int t = r - L * g.side_len[f];
   const int axis = f >> 1, na = g.na[axis];
-  loc[axis] = (f & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
+  const int layer =
+      (f & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
+  Loc l;
   if (g.dim == 2) {
-    loc[1 - axis] = t;
-    loc[2] = 0;
+    if (axis == 0) { l.x = layer; l.y = t; }
+    else { l.x = t; l.y = layer; }
+    l.z = 0;
+  } else if (axis == 0) {
+    l.x = layer; l.z = t / g.ne[1]; l.y = t - l.z * g.ne[1];
+  } else if (axis == 1) {
+    l.y = layer; l.z = t / g.ne[0]; l.x = t - l.z * g.ne[0];
   } else {
-    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-    loc[a2] = t / g.ne[a1];
-    loc[a1] = t - loc[a2] * g.ne[a1];
+    l.z = layer; l.y = t / g.ne[0]; l.x = t - l.y * g.ne[0];
   }
+  return l;
 }
 __device__ inline bool owned_axis(const GeoDev& g, int a, int bc, int loc) {
   return (loc >= g.W || bc == 0) && (loc < g.W + g.na[a] || bc == g.P[a] - 1);
 }
 // global node index of a subdomain-local node, -1 if the subdomain does not
 // own it
-__device__ inline long long owned_global(const GeoDev& g, const int sc[3], const int loc[3]) {
-  long long G = 0, stride = 1;
-  for (int a = 0; a < g.dim; ++a) {
-    if (!owned_axis(g, a, sc[a], loc[a])) return -1;
-    G += (long long)(sc[a] * g.na[a] + loc[a]) * stride;
-    stride *= g.M[a];
+__device__ inline long long owned_global(const GeoDev& g, const Loc& sc, const Loc& l) {
+  if (!owned_axis(g, 0, sc.x, l.x) || !owned_axis(g, 1, sc.y, l.y)) return -1;
+  long long G = (long long)(sc.x * g.na[0] + l.x) + (long long)(sc.y * g.na[1] + l.y) * g.M[0];
+  if (g.dim == 3) {
+    if (!owned_axis(g, 2, sc.z, l.z)) return -1;
+    G += (long long)(sc.z * g.na[2] + l.z) * g.M[0] * g.M[1];
   }
   return G;
 }
@@ -251,17 +272,14 @@ __global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch
     int rem = (int)(r - (long long)k * C * n);
     int col = rem / n, p = rem - col * n;
     cpx<T> v = mk<T>(T(0), T(0));
-    int loc[3];
-    block_node(g, p, k, loc);
+    const Loc loc = block_node(g, p, k);
     if (mode == 2) {
       int d = col0 + col;
       for (int a = 0; a < g.dim; ++a)
         if (iface_dof(g, a, loc) == d) v.re = T(1);
     } else {
       int s = ids[b];
-      int sc[3];
-      sub_coords(g, s, sc);
-      long long G = owned_global(g, sc, loc);
+      long long G = owned_global(g, sub_coords(g, s), loc);
       if (G >= 0) v = ccast<T>(rg[(long long)col * glob + G]);
       if (mode == 1) {
         const cpx<T>* a = accg + ((long long)s * C + col) * g.NI;
@@ -299,10 +317,9 @@ __global__ void k_extract_iface(const cpx<T>* panel, int nbatch, int C, cpx<T>* 
     int b = (int)(idx / ((long long)C * g.NI));
     int r = (int)(idx - (long long)b * C * g.NI);
     int col = r / g.NI, i = r - col * g.NI;
-    int loc[3];
-    dof_node(g, i, loc);
-    const int p = g.dim == 2 ? loc[0] : loc[1] * g.ne[0] + loc[0];
-    const int k = loc[g.dim - 1];
+    const Loc loc = dof_node(g, i);
+    const int p = g.dim == 2 ? loc.x : loc.y * g.ne[0] + loc.x;
+    const int k = g.dim == 2 ? loc.y : loc.z;
     dst[b * dst_sb + (long long)col * dst_ld + i] =
         panel[(((long long)b * (g.K + 1) + k) * C + col) * g.n + p];
   }
@@ -333,10 +350,7 @@ __global__ void k_write_owned(const cpx<T>* panel, int C, c128* glob, long long 
     int k = (int)(r / ((long long)C * n));
     int rem = (int)(r - (long long)k * C * n);
     int col = rem / n, p = rem - col * n;
-    int sc[3], loc[3];
-    sub_coords(g, s, sc);
-    block_node(g, p, k, loc);
-    long long G = owned_global(g, sc, loc);
+    long long G = owned_global(g, sub_coords(g, s), block_node(g, p, k));
     if (G < 0) continue;
     c128 v = ccast<double>(panel[(long long)s * (K + 1) * C * n + r]);
     c128* dst = glob + (long long)col * gn + G;

@@ -644,11 +644,13 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
   int rq = orow - fout.start[q];
   int lay = rq / len, t = rq - lay * len;
   int d = g.side_off[f] + rq;
-  int scc[3] = {s % g.P[0], (s / g.P[0]) % g.P[1], s / (g.P[0] * g.P[1])};
-  int axis = f >> 1;
-  scc[axis] += (f & 1) ? 1 : -1;
-  if (scc[axis] < 0 || scc[axis] >= g.P[axis]) return o;
-  int recv = scc[0] + g.P[0] * (scc[1] + g.P[1] * scc[2]);
+  int c0 = s % g.P[0], c1 = (s / g.P[0]) % g.P[1], c2 = s / (g.P[0] * g.P[1]);
+  const int axis = f >> 1, step = (f & 1) ? 1 : -1;
+  if (axis == 0) c0 += step;
+  else if (axis == 1) c1 += step;
+  else c2 += step;
+  if (c0 < 0 || c0 >= g.P[0] || c1 < 0 || c1 >= g.P[1] || c2 < 0 || c2 >= g.P[2]) return o;
+  int recv = c0 + g.P[0] * (c1 + g.P[1] * c2);
   int fo = f ^ 1;
   size_t rb = (size_t)lq * slot_stride + ((size_t)recv * C + col) * NI;
   if (add_y) o.yo = (long long)(((size_t)s * C + col) * NI + d);
@@ -708,9 +710,12 @@ __global__ __launch_bounds__(512) void k_sweep_step(
     eo[q] = StepOut{-1, -1, -1};
     if (orow < nout && c0 + col < C)
       eo[q] = step_out(g, fout, s, orow, c0 + col, C, L, slot_stride, add_y);
-    ey[q] = eo[q].yo >= 0 ? ybuf[eo[q].yo] : z;
-    ein[q] = eo[q].ino >= 0 ? slots[eo[q].ino] : z;
-    edst[q] = eo[q].dst >= 0 ? slots[eo[q].dst] : z;
+    ey[q] = mk<T>(T(0), T(0));
+    ein[q] = ey[q];
+    edst[q] = ey[q];
+    if (eo[q].yo >= 0) ey[q] = ybuf[eo[q].yo];
+    if (eo[q].ino >= 0) ein[q] = slots[eo[q].ino];
+    if (eo[q].dst >= 0) edst[q] = slots[eo[q].dst];
   }
   // output dof of this lane's A row
   const int row = rtile * 64 + rw * 16 + rr;
@@ -733,7 +738,10 @@ __global__ __launch_bounds__(512) void k_sweep_step(
     for (int idx = tid; idx < 2 * (4 * nks) * 8; idx += 512) {
       int t = idx / (4 * nks * 8), r = idx - t * 4 * nks * 8;
       int k = r >> 3, c = r & 7;
-      cpx<T> v = k < kn ? gsrc[((size_t)(2 * cg + t) * nin + kst + k) * 8 + c] : z;
+      cpx<T> v;
+      v.re = T(0);
+      v.im = T(0);
+      if (k < kn) v = gsrc[((size_t)(2 * cg + t) * nin + kst + k) * 8 + c];
       cpx<T>* row16 = bp + ((size_t)t * LMAX + k) * 16;
       row16[c] = mk<T>(v.re, -v.im);
       row16[c + 8] = mk<T>(v.im, v.re);
@@ -751,7 +759,9 @@ __global__ __launch_bounds__(512) void k_sweep_step(
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         int ks = ks0 + u;
-        a[u] = (ks < kse && 4 * ks + kk < kn && dout >= 0) ? ap[(size_t)ks * astep] : z;
+        a[u].re = T(0);
+        a[u].im = T(0);
+        if (ks < kse && 4 * ks + kk < kn && dout >= 0) a[u] = ap[(size_t)ks * astep];
       }
     };
     auto compute = [&](const cpx<T>(&a)[KB], int ks0) {
@@ -824,6 +834,64 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   }
 }
 
+// Plane-block (3D) sweep step as three launches: the trace sources in plain
+// column layout gplain[bi][col][k] (k over the active input faces), one
+// grouped GEMM out = T[out rows, in columns] g per distinct operator (the
+// row and column maps select the active faces of T), and the routing
+// epilogue below.
+template <class T>
+__global__ void k_trace_src_plain(const cpx<T>* __restrict__ cface,
+                                  const cpx<T>* __restrict__ slots, cpx<T>* gplain, cpx<T>* accg,
+                                  const int* __restrict__ op_of, const int* __restrict__ subs,
+                                  int cnt, int L, int C, FaceSet fin, int nin, GeoDev g) {
+  const int NI = g.NI;
+  const size_t slot_stride = (size_t)g.nsub * C * NI;
+  long long tot = (long long)cnt * C * nin;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int k = (int)(idx % nin);
+    long long bc = idx / nin;
+    int col = (int)(bc % C), bi = (int)(bc / C);
+    int s = subs[bi];
+    int q = fs_find(fin, k);
+    int f = fin.face[q];
+    int len = g.side_len[f];
+    int rq = k - fin.start[q];
+    int lay = rq / len, t = rq - lay * len;
+    int d = g.side_off[f] + rq;
+    int partner = g.side_off[f] + (1 - lay) * len + t;
+    const cpx<T>* sl = slots + (size_t)L * slot_stride + ((size_t)s * C + col) * NI;
+    cpx<T> gv = cface[(size_t)op_of[s] * (NI / 2) + g.side_off[f] / 2 + t] * sl[partner];
+    if (lay == 0) gv = -gv;
+    size_t o = ((size_t)s * C + col) * NI + d;
+    accg[o] = accg[o] + gv;
+    gplain[idx] = gv;
+  }
+}
+
+template <class T>
+__global__ void k_step_scatter(const cpx<T>* __restrict__ out, cpx<T>* slots,
+                               const cpx<T>* __restrict__ ybuf, const int* __restrict__ subs,
+                               int cnt, int L, int C, FaceSet fout, int nout, int add_y,
+                               GeoDev g) {
+  const size_t slot_stride = (size_t)g.nsub * C * g.NI;
+  long long tot = (long long)cnt * C * nout;
+  const cpx<T> z = mk<T>(T(0), T(0));
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int r = (int)(idx % nout);
+    long long bc = idx / nout;
+    int col = (int)(bc % C), bi = (int)(bc / C);
+    StepOut eo = step_out(g, fout, subs[bi], r, col, C, L, slot_stride, add_y);
+    if (eo.dst < 0) continue;
+    cpx<T> v = out[idx];
+    if (eo.yo >= 0) v = v + ybuf[eo.yo];
+    cpx<T> in = z;
+    if (eo.ino >= 0) in = slots[eo.ino];
+    slots[eo.dst] = slots[eo.dst] + (v - in);
+  }
+}
+
 // face coefficients c(face, t) of every distinct operator, contiguous per
 // face: [op][side_off[f] / 2 + t]
 template <class T>
@@ -871,7 +939,7 @@ hipError_t launch_face_coef(hdsw_ctx* c) {
 }
 
 template <class T>
-hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C) {
+hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C) {
   const Geometry& g = c->g;
   FaceSet fin{}, fout{};
   int nin = 0, nout = 0;
@@ -894,6 +962,63 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C) {
   }
   if (nout == 0) return hipSuccess;
   if (fin.n == 0) { fin.n = 1; fin.face[0] = 0; fin.start[0] = 0; }
+  if (g.dim == 3) {
+    const int* subs = c->d_step_subs + off;
+    if (nin > 0) {
+      long long tot = (long long)cnt * C * nin;
+      int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+      hipLaunchKernelGGL(k_trace_src_plain<T>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const cpx<T>*)c->d_cface, (const cpx<T>*)c->d_slots,
+                         (cpx<T>*)c->d_g, (cpx<T>*)c->d_accg, c->d_op_of_sub, subs, cnt, L, C,
+                         fin, nin, c->gd);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const int sidx = L * c->sch.nsteps + st;
+    GemmArgs a{};
+    a.M = nout;
+    a.N = 0;
+    a.Kd = nin;
+    a.A = c->d_T;
+    a.lda = g.NI;
+    a.sAz = (long long)g.NI * g.NI;
+    a.arow = c->d_fmap + c->map_out_off[L];
+    // the active input faces are contiguous column ranges of T
+    a.nseg = fin.n;
+    for (int q = 0; q < fin.n; ++q) {
+      a.seg_k0[q] = fin.start[q];
+      a.seg_c0[q] = g.side_off[fin.face[q]];
+    }
+    a.B = c->d_g;
+    a.ldb = nin;
+    a.sb = (long long)C * nin;
+    a.sBz = 0;
+    a.C = c->d_out;
+    a.ldc = nout;
+    a.sc = (long long)C * nout;
+    a.sCz = 0;
+    a.cpb = C;
+    a.ids = c->d_sg_ids;
+    a.grp_op = c->d_sg_op + c->sg_first[sidx];
+    a.grp_off = c->d_sg_off + c->sg_first[sidx];
+    a.grp_cnt = c->d_sg_cnt + c->sg_first[sidx];
+    a.neg = 0;
+    a.beta = 0;
+    if (nin == 0) {
+      // nothing received yet: the outputs are the source-driven part alone
+      hipError_t e = launch_zero(c, c->d_out, (size_t)cnt * C * nout * sizeof(cpx<T>));
+      if (e != hipSuccess) return e;
+    } else {
+      hipError_t e = gemm<T>(c->stream, a, c->sg_maxcnt[sidx] * C, c->sg_n[sidx]);
+      if (e != hipSuccess) return e;
+    }
+    long long tot = (long long)cnt * C * nout;
+    int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_step_scatter<T>, dim3(blocks), dim3(256), 0, c->stream,
+                       (const cpx<T>*)c->d_out, (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_y, subs,
+                       cnt, L, C, fout, nout, L == 0 ? 1 : 0, c->gd);
+    return hipGetLastError();
+  }
   const int Cp = (C + 15) / 16 * 16;
   {
     long long tot = (long long)cnt * Cp * nin;
@@ -927,7 +1052,7 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int off, int cnt, int C) {
 #define HDSW_INST2(T)                                                          \
   template hipError_t launch_block_solve<T>(hdsw_ctx*, int, const int*, int);  \
   template hipError_t launch_factor_step<T>(hdsw_ctx*, int, int);              \
-  template hipError_t launch_sweep_step<T>(hdsw_ctx*, int, int, int, int);     \
+  template hipError_t launch_sweep_step<T>(hdsw_ctx*, int, int, int, int, int);\
   template hipError_t launch_face_coef<T>(hdsw_ctx*);
 HDSW_INST2(float)
 HDSW_INST2(double)
