@@ -48,18 +48,26 @@ __device__ __forceinline__ long long gemm_acol(const GemmArgs& a, int k) {
 // BK-deep chunks of the sum, double-buffered in LDS (one barrier per
 // chunk): the next chunk's global loads are in flight while the current one
 // is multiplied.
-template <class T, int BK>
-__global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
+// Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
+// its own L2: all column tiles of a row tile are given the same XCD, so the
+// row slab of A is fetched from HBM once.  With ksplit > 1 the sum is cut
+// into ksplit parts whose raw products go to a.part and are added in a
+// fixed order by k_gemm_combine (results do not depend on timing).
+template <class T, int BK, bool TILED>
+__global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
   typedef typename MF<T>::v4 v4;
   constexpr int AL = BK / 4;                 // A elements per thread
   constexpr int BL = BK / 8;                 // B elements per thread
   __shared__ cpx<T> As[2][BK][GPAD];         // [buf][k][row]
   __shared__ cpx<T> Bp[2][BK][GPAD];         // [buf][k][4 groups x 16 operand columns]
-  const int z = blockIdx.z;
+  const int z = blockIdx.z / a.ksplit, kpart = blockIdx.z - z * a.ksplit;
+  const int xcd = blockIdx.x & 7, pos = blockIdx.x >> 3;
+  const int rtile = xcd + 8 * (pos / nct), ctile = pos - (pos / nct) * nct;
+  if (rtile >= nrt) return;
   const int ncols = a.grp_cnt ? a.grp_cnt[z] * a.cpb : a.N;
-  const int col0 = blockIdx.y * GN;
+  const int col0 = ctile * GN;
   if (col0 >= ncols) return;
-  const int row0 = blockIdx.x * GM;
+  const int row0 = rtile * GM;
   const int opz = a.grp_op ? a.grp_op[z] : z;
   const int off = a.grp_off ? a.grp_off[z] : 0;
   const cpx<T>* A = reinterpret_cast<const cpx<T>*>(a.A) + (long long)opz * a.sAz;
@@ -82,6 +90,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
   const int ar = tid & 63, ak = (tid >> 6) * AL;
   const bool arow_ok = row0 + ar < a.M;
   const cpx<T>* acol = A + (arow_ok ? (a.arow ? a.arow[row0 + ar] : row0 + ar) : 0);
+  const cpx<T>* atile = TILED ? A + (long long)a.a_rt[rtile] * a.a_tile_ld * (GM * BK) : nullptr;
 
   cpx<T> ra[AL], rb[BL];
   v4 accR[4], accI[4];
@@ -91,15 +100,22 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
     accI[g] = accR[g];
   }
   const int mr = wave * 16 + (lane & 15), mk4 = lane >> 4, mc = lane & 15;
-  const int nch = (a.Kd + BK - 1) / BK;
+  const int nch_all = (a.Kd + BK - 1) / BK;
+  const int ch0 = (int)((long long)nch_all * kpart / a.ksplit);
+  const int ch1 = (int)((long long)nch_all * (kpart + 1) / a.ksplit);
 
 #define HDSW_GEMM_LOAD(k0)                                                       \
   {                                                                              \
-    _Pragma("unroll") for (int u = 0; u < AL; ++u) {                             \
-      int k = (k0) + ak + u;                                                     \
-      ra[u].re = T(0);                                                           \
-      ra[u].im = T(0);                                                           \
-      if (arow_ok && k < a.Kd) ra[u] = acol[gemm_acol(a, k) * a.lda];            \
+    if (TILED) {                                                                 \
+      const cpx<T>* tp = atile + (long long)a.a_kt[(k0) / BK] * (GM * BK) + ar;  \
+      _Pragma("unroll") for (int u = 0; u < AL; ++u) ra[u] = tp[(ak + u) * GM];  \
+    } else {                                                                     \
+      _Pragma("unroll") for (int u = 0; u < AL; ++u) {                           \
+        int k = (k0) + ak + u;                                                   \
+        ra[u].re = T(0);                                                         \
+        ra[u].im = T(0);                                                         \
+        if (arow_ok && k < a.Kd) ra[u] = acol[gemm_acol(a, k) * a.lda];          \
+      }                                                                          \
     }                                                                            \
     _Pragma("unroll") for (int u = 0; u < BL; ++u) {                             \
       int k = (k0) + bk + u;                                                     \
@@ -118,12 +134,14 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
     }                                                                            \
   }
 
-  HDSW_GEMM_LOAD(0);
-  HDSW_GEMM_STORE(0);
+  if (ch0 < ch1) {
+    HDSW_GEMM_LOAD(ch0 * BK);
+    HDSW_GEMM_STORE(0);
+  }
   __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) HDSW_GEMM_LOAD((ch + 1) * BK);
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int buf = (ch - ch0) & 1;
+    if (ch + 1 < ch1) HDSW_GEMM_LOAD((ch + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const cpx<T> av = As[buf][ks * 4 + mk4][mr];
@@ -134,7 +152,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
         accI[g] = MF<T>::mfma(av.im, p.im, accI[g]);
       }
     }
-    if (ch + 1 < nch) HDSW_GEMM_STORE(buf ^ 1);
+    if (ch + 1 < ch1) HDSW_GEMM_STORE(buf ^ 1);
     __syncthreads();
   }
 #undef HDSW_GEMM_LOAD
@@ -156,6 +174,21 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
   __syncthreads();
   const int orow = tid & 63, oc = tid >> 6;
   if (row0 + orow >= a.M) return;
+  if (a.ksplit > 1) {
+    // raw partial product: part[kpart][z][j][row], j < column tiles x GN
+    cpx<T>* P = reinterpret_cast<cpx<T>*>(a.part) +
+                ((long long)kpart * gridDim.z / a.ksplit + z) * a.part_cols * a.M;
+#pragma unroll
+    for (int q = 0; q < GN / 4; ++q) {
+      int c = oc * (GN / 4) + q;
+      int j = col0 + c;
+      if (j >= ncols) break;
+      P[(long long)j * a.M + row0 + orow] = Cs[c][orow];
+    }
+    return;
+  }
+  const int crow = a.c_row ? a.c_row[row0 + orow] : row0 + orow;
+  if (crow < 0) return;
 #pragma unroll
   for (int q = 0; q < GN / 4; ++q) {
     int c = oc * (GN / 4) + q;
@@ -163,7 +196,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
     if (j >= ncols) break;
     int e = j / a.cpb, jj = j - e * a.cpb;
     int eid = a.ids ? a.ids[off + e] : e;
-    cpx<T>* dst = C + (long long)eid * a.sc + (long long)jj * a.ldc + row0 + orow;
+    cpx<T>* dst = C + (long long)eid * a.sc + (long long)jj * a.ldc + crow;
     cpx<T> v = Cs[c][orow];
     if (a.neg) v = -v;
     if (a.beta) v = *dst + v;
@@ -172,11 +205,62 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a) {
 }
 
 template <class T>
-hipError_t gemm(hipStream_t st, const GemmArgs& a, int maxcols, int ngroups) {
-  if (a.M <= 0 || maxcols <= 0 || ngroups <= 0) return hipSuccess;
-  dim3 grid((a.M + GM - 1) / GM, (maxcols + GN - 1) / GN, ngroups);
+int gemm_bk() {
+  return sizeof(T) == 4 ? 32 : 16;
+}
+
+// C = beta C + s (sum of the partial products), in a fixed order
+template <class T>
+__global__ void k_gemm_combine(GemmArgs a, int ngroups, int maxcols) {
+  const long long per = (long long)maxcols * a.M;
+  const long long tot = per * ngroups;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int z = (int)(idx / per);
+    long long r = idx - z * per;
+    int j = (int)(r / a.M), row = (int)(r - (long long)j * a.M);
+    const int ncols = a.grp_cnt ? a.grp_cnt[z] * a.cpb : a.N;
+    if (j >= ncols) continue;
+    const int crow = a.c_row ? a.c_row[row] : row;
+    if (crow < 0) continue;
+    const cpx<T>* P = reinterpret_cast<const cpx<T>*>(a.part);
+    cpx<T> v = P[((long long)z * a.part_cols + j) * a.M + row];
+    for (int p = 1; p < a.ksplit; ++p)
+      v = v + P[(((long long)p * ngroups + z) * a.part_cols + j) * a.M + row];
+    const int off = a.grp_off ? a.grp_off[z] : 0;
+    int e = j / a.cpb, jj = j - e * a.cpb;
+    int eid = a.ids ? a.ids[off + e] : e;
+    cpx<T>* C = reinterpret_cast<cpx<T>*>(a.C) + (long long)z * a.sCz;
+    cpx<T>* dst = C + (long long)eid * a.sc + (long long)jj * a.ldc + crow;
+    if (a.neg) v = -v;
+    if (a.beta) v = *dst + v;
+    *dst = v;
+  }
+}
+
+// a.ksplit > 1 needs a.part with ksplit * ngroups * maxcols * M elements
+template <class T>
+hipError_t gemm(hipStream_t st, const GemmArgs& a_in, int maxcols, int ngroups) {
+  if (a_in.M <= 0 || maxcols <= 0 || ngroups <= 0) return hipSuccess;
+  GemmArgs a = a_in;
+  if (a.ksplit < 1) a.ksplit = 1;
+  if (a.ksplit > 1 && !a.part) return hipErrorInvalidValue;
+  a.part_cols = maxcols;
   constexpr int BK = sizeof(T) == 4 ? 32 : 16;
-  hipLaunchKernelGGL((k_cgemm<T, BK>), grid, dim3(256), 0, st, a);
+  const int nrt = (a.M + GM - 1) / GM, nct = (maxcols + GN - 1) / GN;
+  dim3 grid(8 * ((nrt + 7) / 8) * nct, 1, ngroups * a.ksplit);
+  if (a.a_rt) {
+    // tiled A: whole tiles only
+    if (a.M % GM != 0 || a.Kd % BK != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_cgemm<T, BK, true>), grid, dim3(256), 0, st, a, nrt, nct);
+  } else {
+    hipLaunchKernelGGL((k_cgemm<T, BK, false>), grid, dim3(256), 0, st, a, nrt, nct);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.ksplit == 1) return e;
+  long long tot = (long long)ngroups * maxcols * a.M;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_gemm_combine<T>, dim3(blocks), dim3(256), 0, st, a, ngroups, maxcols);
   return hipGetLastError();
 }
 
@@ -398,6 +482,64 @@ hipError_t launch_big_factor(hdsw_ctx* c, void* rbuf) {
   return hipSuccess;
 }
 
+// ------------------------------------------------------------ tiled T
+// T(i, j) of operator op into its tile: face f of a row dof i starts at the
+// padded row t_roff[f], face of the column dof j at the padded column
+// t_koff[f]; tiles are 64 rows x TK columns, k-major inside, row tiles
+// outermost.  Padding stays zero (the buffer is cleared first).
+struct TileGeo {
+  int roff[6], koff[6], nkt, tk;
+};
+__device__ inline int face_of(const GeoDev& g, int i) {
+  int f = 0;
+  while (f < 2 * g.dim - 1 && i >= g.side_off[f + 1]) ++f;
+  return f;
+}
+template <class T>
+__global__ void k_extract_tiled(const cpx<T>* panel, int C, cpx<T>* Tt, int col0, GeoDev g,
+                                TileGeo tg) {
+  long long tot = (long long)C * g.NI;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int col = (int)(idx / g.NI), i = (int)(idx - (long long)col * g.NI);
+    // node of dof i: plane k, in-plane p (3D)
+    int f = face_of(g, i);
+    int r = i - g.side_off[f];
+    int L = r / g.side_len[f], t = r - L * g.side_len[f];
+    int axis = f >> 1, na = g.na[axis];
+    int layer = (f & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
+    int x, y, z;
+    if (axis == 0) { x = layer; z = t / g.ne[1]; y = t - z * g.ne[1]; }
+    else if (axis == 1) { y = layer; z = t / g.ne[0]; x = t - z * g.ne[0]; }
+    else { z = layer; y = t / g.ne[0]; x = t - y * g.ne[0]; }
+    cpx<T> v = panel[((long long)z * C + col) * g.n + (long long)y * g.ne[0] + x];
+    int j = col0 + col;
+    int fj = face_of(g, j);
+    int prow = tg.roff[f] + r;
+    int pcol = tg.koff[fj] + (j - g.side_off[fj]);
+    long long tile = (long long)(prow >> 6) * tg.nkt + pcol / tg.tk;
+    Tt[tile * 64 * tg.tk + (long long)(pcol % tg.tk) * 64 + (prow & 63)] = v;
+  }
+}
+
+template <class T>
+hipError_t launch_extract_tiled(hdsw_ctx* c, int C, int op, int col0) {
+  const Geometry& g = c->g;
+  TileGeo tg;
+  for (int f = 0; f < 6; ++f) {
+    tg.roff[f] = c->t_roff[f];
+    tg.koff[f] = c->t_koff[f];
+  }
+  tg.nkt = c->t_nkt;
+  tg.tk = c->t_tk;
+  cpx<T>* Tt = (cpx<T>*)c->d_T + (long long)op * c->t_nrt * 64 * (long long)c->t_nkt * c->t_tk;
+  long long tot = (long long)C * g.NI;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_extract_tiled<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (const cpx<T>*)c->d_panel, C, Tt, col0, c->gd, tg);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ solve
 // scratch line K of each panel entry b (operator ops[b]):
 //   forward  t = f_k - B_k w_{k-1}  (k > 0),  t = f_0
@@ -469,6 +611,13 @@ hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int
       a.grp_cnt = grp_cnt;
       a.neg = fwd ? 0 : 1;
       a.beta = fwd ? 0 : 1;
+      // too few output tiles to fill the chip: split the sum
+      const long long tiles = (long long)((n + 63) / 64) * ((maxcnt * C + 31) / 32) * ngroups;
+      int ks = (int)std::min<long long>(4, std::max<long long>(1, (512 + tiles - 1) / tiles));
+      while (ks > 1 && (size_t)ks * ngroups * maxcnt * C * n * sizeof(cpx<T>) > c->gpart_bytes)
+        --ks;
+      a.ksplit = ks;
+      a.part = c->d_gpart;
       e = gemm<T>(c->stream, a, maxcnt * C, ngroups);
       if (e != hipSuccess) return e;
     }
@@ -478,6 +627,8 @@ hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int
 
 #define HDSW_INST3(T)                                                                      \
   template hipError_t gemm<T>(hipStream_t, const GemmArgs&, int, int);                     \
+  template int gemm_bk<T>();                                                               \
+  template hipError_t launch_extract_tiled<T>(hdsw_ctx*, int, int, int);                   \
   template hipError_t launch_big_factor<T>(hdsw_ctx*, void*);                              \
   template hipError_t launch_big_solve<T>(hdsw_ctx*, int, const int*, const int*,          \
                                           const int*, const int*, const int*, int, int, int);

@@ -432,6 +432,20 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   size_t xbytes = g.dim == 2 ? (size_t)c->nops * g.K * g.nP * g.nP * e
                              : (size_t)c->nops * g.K * g.n * g.n * e;
   size_t tbytes = (size_t)c->nops * g.NI * g.NI * e;
+  if (g.dim == 3) {
+    // T in 64 x t_tk tiles, every face padded to whole tiles
+    c->t_tk = opt->precision == HDSW_MIXED ? 32 : 16;
+    int ro = 0, ko = 0;
+    for (int f = 0; f < 6; ++f) {
+      c->t_roff[f] = ro;
+      c->t_koff[f] = ko;
+      ro += (2 * g.side_len[f] + 63) / 64 * 64;
+      ko += (2 * g.side_len[f] + c->t_tk - 1) / c->t_tk * c->t_tk;
+    }
+    c->t_nrt = ro / 64;
+    c->t_nkt = ko / c->t_tk;
+    tbytes = (size_t)c->nops * ro * ko * e;
+  }
   c->factor_bytes = xbytes + tbytes;
   void* p;
 #define SALLOC(dst, bytes)                     \
@@ -473,15 +487,38 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   std::vector<int> fmap, sg_op, sg_off, sg_cnt, sg_ids;
   if (g.dim == 3) {
     const Schedule& sc = c->sch;
+    const int tk = c->t_tk;
     for (int L = 0; L < sc.nsweeps; ++L) {
-      c->map_out_off.push_back((int)fmap.size());
+      // row tiles of the output faces, k tiles of the input faces, and the
+      // padded output row -> unpadded step output row map
+      c->tm_rt_off.push_back((int)fmap.size());
+      int nrt = 0, mpad = 0, nkt = 0;
       for (int f = 0; f < 2 * g.dim; ++f)
-        if (sc.lprime[L * 6 + f] >= 0)
-          for (int r = 0; r < 2 * g.side_len[f]; ++r) fmap.push_back(g.side_off[f] + r);
-      c->map_in_off.push_back((int)fmap.size());
+        if (sc.lprime[L * 6 + f] >= 0) {
+          int rf = (2 * g.side_len[f] + 63) / 64;
+          for (int q = 0; q < rf; ++q) fmap.push_back(c->t_roff[f] / 64 + q);
+          nrt += rf;
+        }
+      c->tm_kt_off.push_back((int)fmap.size());
       for (int f = 0; f < 2 * g.dim; ++f)
-        if (sc.in_active[L * 6 + f])
-          for (int r = 0; r < 2 * g.side_len[f]; ++r) fmap.push_back(g.side_off[f] + r);
+        if (sc.in_active[L * 6 + f]) {
+          int kf = (2 * g.side_len[f] + tk - 1) / tk;
+          for (int q = 0; q < kf; ++q) fmap.push_back(c->t_koff[f] / tk + q);
+          nkt += kf;
+        }
+      c->tm_row_off.push_back((int)fmap.size());
+      int uo = 0;
+      for (int f = 0; f < 2 * g.dim; ++f)
+        if (sc.lprime[L * 6 + f] >= 0) {
+          int len = 2 * g.side_len[f];
+          int rp = (len + 63) / 64 * 64;
+          for (int r = 0; r < rp; ++r) fmap.push_back(r < len ? uo + r : -1);
+          uo += len;
+          mpad += rp;
+        }
+      c->tm_nrt.push_back(nrt);
+      c->tm_nkt.push_back(nkt);
+      c->tm_mpad.push_back(mpad);
       for (int st = 0; st < sc.nsteps; ++st) {
         int off = sc.step_off[L * sc.nsteps + st], cnt = sc.step_cnt[L * sc.nsteps + st];
         c->sg_first.push_back((int)sg_op.size());
@@ -505,7 +542,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
     if (fmap.empty()) fmap.push_back(0);
     if (sg_op.empty()) { sg_op.push_back(0); sg_off.push_back(0); sg_cnt.push_back(0); }
     if (sg_ids.empty()) sg_ids.push_back(0);
-    SALLOC(c->d_fmap, fmap.size() * sizeof(int));
+    SALLOC(c->d_tmap, fmap.size() * sizeof(int));
     SALLOC(c->d_sg_op, sg_op.size() * sizeof(int));
     SALLOC(c->d_sg_off, sg_off.size() * sizeof(int));
     SALLOC(c->d_sg_cnt, sg_cnt.size() * sizeof(int));
@@ -541,7 +578,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   up(c->d_grp_cnt, grp_cnt.data(), c->ngrp * sizeof(int));
   up(c->d_grp_ids, grp_ids.data(), g.nsub * sizeof(int));
   if (g.dim == 3) {
-    up(c->d_fmap, fmap.data(), fmap.size() * sizeof(int));
+    up(c->d_tmap, fmap.data(), fmap.size() * sizeof(int));
     up(c->d_sg_op, sg_op.data(), sg_op.size() * sizeof(int));
     up(c->d_sg_off, sg_off.data(), sg_off.size() * sizeof(int));
     up(c->d_sg_cnt, sg_cnt.data(), sg_cnt.size() * sizeof(int));
@@ -594,17 +631,28 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
   ACHK(dev_alloc(c, &tmp, per_col * ct));
   void* saved = c->d_panel;
   c->d_panel = tmp;
+  if (g.dim == 3) {
+    hipError_t rz = launch_zero(
+        c, c->d_T, (size_t)c->nops * c->t_nrt * 64 * (size_t)c->t_nkt * c->t_tk * e);
+    if (rz != hipSuccess) {
+      c->d_panel = saved;
+      dev_free(c, tmp);
+      c->sticky = HDSW_EDEVICE;
+      return HDSW_EDEVICE;
+    }
+  }
   for (int op = 0; op < c->nops; ++op) {
     for (int col0 = 0; col0 < g.NI; col0 += ct) {
       int nc = std::min(ct, g.NI - col0);
       hipError_t r1 = launch_fill_panel<T>(c, 2, 1, c->d_all_ops + op, nc, nullptr, col0);
       hipError_t r2 = r1 == hipSuccess ? launch_block_solve<T>(c, 1, c->d_all_ops + op, nc) : r1;
-      hipError_t r3 = r2 == hipSuccess
-                          ? launch_extract_iface<T>(c, 1, nc,
-                                                    (cpx<T>*)c->d_T + (size_t)op * g.NI * g.NI +
-                                                        (size_t)col0 * g.NI,
-                                                    0, g.NI)
-                          : r2;
+      hipError_t r3 = r2;
+      if (r2 == hipSuccess && g.dim == 3) {
+        r3 = launch_extract_tiled<T>(c, nc, op, col0);
+      } else if (r2 == hipSuccess) {
+        r3 = launch_extract_iface<T>(
+            c, 1, nc, (cpx<T>*)c->d_T + (size_t)op * g.NI * g.NI + (size_t)col0 * g.NI, 0, g.NI);
+      }
       if (r3 != hipSuccess) {
         c->d_panel = saved;
         dev_free(c, tmp);
@@ -634,10 +682,11 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   if (C > c->Cmax) {
-    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_y, c->d_out,
+    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_y, c->d_out, c->d_gpart,
                     c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
     for (void* p : ptrs) dev_free(c, p);
-    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_y = c->d_out = nullptr;
+    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_y = c->d_out = c->d_gpart = nullptr;
+    c->gpart_bytes = 0;
     c->d_xg = c->d_rg = c->d_bg = nullptr;
     c->d_part = c->d_norm = nullptr;
     c->Cmax = 0;
@@ -652,10 +701,18 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     size_t iface = (size_t)g.nsub * C * g.NI * e;
     WALLOC(c->d_panel, (size_t)g.nsub * (g.K + 1) * C * g.n * e);
     WALLOC(c->d_slots, iface * c->sch.nsweeps);
-    WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) * g.NI * e);
+    WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) *
+                       (g.dim == 3 ? (size_t)c->t_nkt * c->t_tk : (size_t)g.NI) * e);
     WALLOC(c->d_accg, iface);
     WALLOC(c->d_y, iface);
-    if (g.dim == 3) WALLOC(c->d_out, iface);
+    if (g.dim == 3) {
+      WALLOC(c->d_out, iface);
+      // split-sum partials of the plane solves: up to 4 parts of every
+      // operator group's columns
+      size_t gp = (size_t)4 * c->nops * c->grp_maxcnt * C * g.n * e;
+      WALLOC(c->d_gpart, gp);
+      c->gpart_bytes = gp;
+    }
     WALLOC(c->d_xg, (size_t)C * g.glob_nodes * sizeof(c128));
     WALLOC(c->d_rg, (size_t)C * g.glob_nodes * sizeof(c128));
     WALLOC(c->d_bg, (size_t)C * g.glob_nodes * sizeof(c128));
@@ -751,6 +808,7 @@ static size_t max_cols(hdsw_ctx* c) {
                    (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 3 : 2)) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
+  if (g.dim == 3) per_col += (size_t)4 * c->nops * c->grp_maxcnt * g.n * e;
   size_t used = c->alloc_bytes;
   // workspaces currently held can be reused
   if (c->Cmax > 0) used -= std::min(used, (size_t)c->Cmax * per_col);

@@ -187,13 +187,17 @@ struct hdsw_ctx {
   int* d_piv = nullptr;             // [nops][n] Gauss-Jordan row interchanges
   // plane-block (3D) sweep steps: T rows / columns of the active faces per
   // sweep, and the subdomains of every step grouped by operator
-  int* d_fmap = nullptr;
-  std::vector<int> map_out_off, map_in_off;   // per sweep, into d_fmap
   int* d_sg_op = nullptr;
   int* d_sg_off = nullptr;
   int* d_sg_cnt = nullptr;
   int* d_sg_ids = nullptr;                     // step-local entry indices
   std::vector<int> sg_first, sg_n, sg_maxcnt;  // per (sweep, step)
+  // 3D: T in tiles of 64 rows x t_tk columns, faces padded to whole tiles
+  int t_tk = 32, t_nrt = 0, t_nkt = 0;
+  int t_roff[6] = {0}, t_koff[6] = {0};         // padded face offsets
+  int* d_tmap = nullptr;                        // per sweep: row tiles, k tiles, row map
+  std::vector<int> tm_rt_off, tm_kt_off, tm_row_off, tm_nrt, tm_nkt, tm_mpad;
+
 
   // precision-dependent factors: element type cpx<float> or cpx<double>
   void* d_X = nullptr;              // [nops][K][nP][nP] column-major blocks
@@ -210,6 +214,8 @@ struct hdsw_ctx {
   void* d_accg = nullptr;           // [nsub][C][NI] accumulated sources
   void* d_y = nullptr;              // [nsub][C][NI] source-driven outputs
   void* d_out = nullptr;            // [nsub][C][NI] step outputs (3D)
+  void* d_gpart = nullptr;          // split-sum partial products (3D plane solves)
+  size_t gpart_bytes = 0;
   hdsw::c128* d_xg = nullptr;       // [C][glob] iterate (FP64)
   hdsw::c128* d_rg = nullptr;       // [C][glob] residual (FP64)
   hdsw::c128* d_bg = nullptr;       // [C][glob] right-hand side (FP64)
@@ -261,10 +267,27 @@ struct GemmArgs {
   int nseg;
   int seg_k0[6];
   int seg_c0[6];
+  // tiled A (64-row x BK-deep tiles stored contiguously, k-major inside a
+  // tile): row tile of workgroup x = a_rt[x], chunk ch = tile a_kt[ch], tile
+  // (rt, kt) at A + (rt * a_tile_ld + kt) * 64 * BK; null = plain layout
+  const int* a_rt;
+  const int* a_kt;
+  long long a_tile_ld;
+  // output row r goes to row c_row[r] of C (-1: dropped); null = r
+  const int* c_row;
+  // split of the sum into ksplit parts (0 or 1: none); part holds the
+  // partial products, ksplit * groups * columns * M elements
+  int ksplit;
+  void* part;
+  int part_cols;
 };
 
 template <class T>
 hipError_t gemm(hipStream_t st, const GemmArgs& a, int maxcols, int ngroups);
+template <class T>
+int gemm_bk();
+template <class T>
+hipError_t launch_extract_tiled(hdsw_ctx* c, int C, int op, int col0);
 
 // ----- launchers (kernels.hip) ------------------------------------------
 hipError_t launch_assemble(hdsw_ctx* c);

@@ -835,10 +835,10 @@ __global__ __launch_bounds__(512) void k_sweep_step(
 }
 
 // Plane-block (3D) sweep step as three launches: the trace sources in plain
-// column layout gplain[bi][col][k] (k over the active input faces), one
-// grouped GEMM out = T[out rows, in columns] g per distinct operator (the
-// row and column maps select the active faces of T), and the routing
-// epilogue below.
+// column layout gplain[bi][col][k] (k over the active input faces, each
+// face padded to whole tiles), one grouped GEMM out = T[out rows, in
+// columns] g per distinct operator on the tiled T (the row-tile and k-tile
+// maps select the active faces), and the routing epilogue below.
 template <class T>
 __global__ void k_trace_src_plain(const cpx<T>* __restrict__ cface,
                                   const cpx<T>* __restrict__ slots, cpx<T>* gplain, cpx<T>* accg,
@@ -857,6 +857,10 @@ __global__ void k_trace_src_plain(const cpx<T>* __restrict__ cface,
     int f = fin.face[q];
     int len = g.side_len[f];
     int rq = k - fin.start[q];
+    if (rq >= 2 * len) {             // padding of the face to whole tiles
+      gplain[idx] = mk<T>(T(0), T(0));
+      continue;
+    }
     int lay = rq / len, t = rq - lay * len;
     int d = g.side_off[f] + rq;
     int partner = g.side_off[f] + (1 - lay) * len + t;
@@ -964,34 +968,39 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
   if (fin.n == 0) { fin.n = 1; fin.face[0] = 0; fin.start[0] = 0; }
   if (g.dim == 3) {
     const int* subs = c->d_step_subs + off;
+    // input faces in the padded k space of the tiled T
+    const int tk = c->t_tk;
+    FaceSet finp = fin;
+    int ninp = 0;
+    for (int q = 0; q < fin.n && nin > 0; ++q) {
+      finp.start[q] = ninp;
+      ninp += (2 * g.side_len[fin.face[q]] + tk - 1) / tk * tk;
+    }
     if (nin > 0) {
-      long long tot = (long long)cnt * C * nin;
+      long long tot = (long long)cnt * C * ninp;
       int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
       hipLaunchKernelGGL(k_trace_src_plain<T>, dim3(blocks), dim3(256), 0, c->stream,
                          (const cpx<T>*)c->d_cface, (const cpx<T>*)c->d_slots,
                          (cpx<T>*)c->d_g, (cpx<T>*)c->d_accg, c->d_op_of_sub, subs, cnt, L, C,
-                         fin, nin, c->gd);
+                         finp, ninp, c->gd);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     const int sidx = L * c->sch.nsteps + st;
     GemmArgs a{};
-    a.M = nout;
+    a.M = c->tm_mpad[L];
     a.N = 0;
-    a.Kd = nin;
+    a.Kd = ninp;
     a.A = c->d_T;
-    a.lda = g.NI;
-    a.sAz = (long long)g.NI * g.NI;
-    a.arow = c->d_fmap + c->map_out_off[L];
-    // the active input faces are contiguous column ranges of T
-    a.nseg = fin.n;
-    for (int q = 0; q < fin.n; ++q) {
-      a.seg_k0[q] = fin.start[q];
-      a.seg_c0[q] = g.side_off[fin.face[q]];
-    }
+    a.lda = 0;
+    a.sAz = (long long)c->t_nrt * 64 * (long long)c->t_nkt * tk;
+    a.a_rt = c->d_tmap + c->tm_rt_off[L];
+    a.a_kt = c->d_tmap + c->tm_kt_off[L];
+    a.a_tile_ld = c->t_nkt;
+    a.c_row = c->d_tmap + c->tm_row_off[L];
     a.B = c->d_g;
-    a.ldb = nin;
-    a.sb = (long long)C * nin;
+    a.ldb = ninp;
+    a.sb = (long long)C * ninp;
     a.sBz = 0;
     a.C = c->d_out;
     a.ldc = nout;
@@ -1009,6 +1018,7 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
       hipError_t e = launch_zero(c, c->d_out, (size_t)cnt * C * nout * sizeof(cpx<T>));
       if (e != hipSuccess) return e;
     } else {
+      if (tk != gemm_bk<T>()) return hipErrorInvalidValue;
       hipError_t e = gemm<T>(c->stream, a, c->sg_maxcnt[sidx] * C, c->sg_n[sidx]);
       if (e != hipSuccess) return e;
     }
