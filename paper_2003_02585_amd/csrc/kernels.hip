@@ -403,19 +403,15 @@ hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C) {
   return hipGetLastError();
 }
 
-// r = b - S x with the global operator's coefficients formed on the fly
+// r = b - S x with the global operator's coefficients formed on the fly,
+// once per node for all C columns (thread per node, columns in a loop)
 __global__ void k_residual2d(const c128* b, const c128* x, c128* r, int C,
                              const c128* al, int o_nx, int o_hx, int o_ny, int o_hy,
                              const double* kap, GeoDev g, double h2, long long gn) {
   const int Mx = g.M[0], My = g.M[1];
-  long long tot = (long long)C * gn;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int col = (int)(idx / gn);
-    long long G = idx - col * gn;
+  for (long long G = blockIdx.x * (long long)blockDim.x + threadIdx.x; G < gn;
+       G += (long long)gridDim.x * blockDim.x) {
     int gy = (int)(G / Mx), gx = (int)(G - (long long)gy * Mx);
-    const c128* xc = x + (long long)col * gn;
-    c128 u = xc[G];
     c128 anx = al[o_nx + gx], any = al[o_ny + gy];
     c128 axl = any * cinv(al[o_hx + gx]);
     c128 axr = any * cinv(al[o_hx + gx + 1]);
@@ -425,16 +421,25 @@ __global__ void k_residual2d(const c128* b, const c128* x, c128* r, int C,
     int iy = min(max(gy - g.W, 0), g.N[1] - 1);
     double kk = kap[(long long)iy * g.N[0] + ix];
     c128 J = anx * any;
-    c128 su = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im) * u;
-    c128 z = mk<double>(0.0, 0.0);
-    c128 ul = gx > 0 ? xc[G - 1] : z;
-    c128 ur = gx < Mx - 1 ? xc[G + 1] : z;
-    c128 ud = gy > 0 ? xc[G - Mx] : z;
-    c128 uu = gy < My - 1 ? xc[G + Mx] : z;
-    su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud);
-    r[idx] = b ? (b[idx] - su) : su;
+    c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
+    const bool hl = gx > 0, hr = gx < Mx - 1, hd = gy > 0, hu = gy < My - 1;
+    for (int col = 0; col < C; ++col) {
+      const c128* xc = x + (long long)col * gn;
+      c128 u = xc[G];
+      c128 z = mk<double>(0.0, 0.0);
+      c128 ul = z, ur = z, ud = z, uu = z;
+      if (hl) ul = xc[G - 1];
+      if (hr) ur = xc[G + 1];
+      if (hd) ud = xc[G - Mx];
+      if (hu) uu = xc[G + Mx];
+      c128 su = d * u;
+      su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud);
+      long long idx = (long long)col * gn + G;
+      r[idx] = b ? (b[idx] - su) : su;
+    }
   }
 }
+
 // 3D: 7-point operator of eq. (PML3) on the global grid
 __global__ void k_residual3d(const c128* b, const c128* x, c128* r, int C, const c128* al,
                              AlphaOff ao, const double* kap, GeoDev g, double h2,
@@ -443,16 +448,11 @@ __global__ void k_residual3d(const c128* b, const c128* x, c128* r, int C, const
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
   const long long Mxy = (long long)Mx * My;
   const int onx = o[0], ohx = o[1], ony = o[2], ohy = o[3], onz = o[4], ohz = o[5];
-  long long tot = (long long)C * gn;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int col = (int)(idx / gn);
-    long long G = idx - col * gn;
+  for (long long G = blockIdx.x * (long long)blockDim.x + threadIdx.x; G < gn;
+       G += (long long)gridDim.x * blockDim.x) {
     int gz = (int)(G / Mxy);
     long long rem = G - gz * Mxy;
     int gy = (int)(rem / Mx), gx = (int)(rem - (long long)gy * Mx);
-    const c128* xc = x + (long long)col * gn;
-    c128 u = xc[G];
     c128 anx = al[onx + gx], any = al[ony + gy], anz = al[onz + gz];
     c128 axl = any * anz * cinv(al[ohx + gx]);
     c128 axr = any * anz * cinv(al[ohx + gx + 1]);
@@ -465,22 +465,31 @@ __global__ void k_residual3d(const c128* b, const c128* x, c128* r, int C, const
     int iz = min(max(gz - g.W, 0), g.N[2] - 1);
     double kk = kap[((long long)iz * g.N[1] + iy) * g.N[0] + ix];
     c128 J = anx * any * anz;
-    c128 su = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im) * u;
-    c128 z = mk<double>(0.0, 0.0);
-    c128 ul = gx > 0 ? xc[G - 1] : z;
-    c128 ur = gx < Mx - 1 ? xc[G + 1] : z;
-    c128 ud = gy > 0 ? xc[G - Mx] : z;
-    c128 uu = gy < My - 1 ? xc[G + Mx] : z;
-    c128 ub = gz > 0 ? xc[G - Mxy] : z;
-    c128 uf = gz < Mz - 1 ? xc[G + Mxy] : z;
-    su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud) +
-         azr * (uf - u) - azl * (u - ub);
-    r[idx] = b ? (b[idx] - su) : su;
+    c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
+    const bool hl = gx > 0, hr = gx < Mx - 1, hd = gy > 0, hu = gy < My - 1, hb = gz > 0,
+               hf = gz < Mz - 1;
+    for (int col = 0; col < C; ++col) {
+      const c128* xc = x + (long long)col * gn;
+      c128 u = xc[G];
+      c128 z = mk<double>(0.0, 0.0);
+      c128 ul = z, ur = z, ud = z, uu = z, ub = z, uf = z;
+      if (hl) ul = xc[G - 1];
+      if (hr) ur = xc[G + 1];
+      if (hd) ud = xc[G - Mx];
+      if (hu) uu = xc[G + Mx];
+      if (hb) ub = xc[G - Mxy];
+      if (hf) uf = xc[G + Mxy];
+      c128 su = d * u;
+      su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud) +
+           azr * (uf - u) - azl * (u - ub);
+      long long idx = (long long)col * gn + G;
+      r[idx] = b ? (b[idx] - su) : su;
+    }
   }
 }
 
 hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, int C) {
-  long long tot = (long long)C * c->g.glob_nodes;
+  long long tot = c->g.glob_nodes;
   int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
   if (c->g.dim == 3) {
     AlphaOff ao;
@@ -496,6 +505,7 @@ hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, i
                      c->g.h * c->g.h, c->g.glob_nodes);
   return hipGetLastError();
 }
+
 
 // per-column 2-norms, deterministic two-pass reduction
 __global__ void k_norm_part(const c128* v, long long gn, int nblk, double* part) {

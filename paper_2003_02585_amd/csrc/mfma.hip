@@ -670,20 +670,22 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
 // pair per 4-deep slice.  Four accumulators (two tiles x real/imaginary part
 // of X) keep dependent MFMAs apart; the T columns of a face are contiguous,
 // so its operand is walked by pointer increments.
-template <class T, int KB>
+template <class T, int KB, int RW>
 __global__ __launch_bounds__(512) void k_sweep_step(
     const cpx<T>* __restrict__ Tm, const cpx<T>* __restrict__ gbuf, cpx<T>* slots,
     const cpx<T>* __restrict__ ybuf, const int* __restrict__ op_of,
     const int* __restrict__ subs, int L, int C, int Cp, FaceSet fin, int nin, FaceSet fout,
     int nout, int add_y, int LMAX, int nsub_chunks, GeoDev g) {
   typedef typename MF<T>::v4 v4;
+  // RW 16-row tiles per workgroup; the 8 waves split the sum in KH parts
+  constexpr int KH = 8 / RW, RWS = 16 * RW, NQ = (RWS * 16 + 511) / 512;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* bp = reinterpret_cast<cpx<T>*>(smem_raw);        // [2 tiles][LMAX][16] pairs
   const int NI = g.NI;
   // XCD-aware mapping: workgroups are dispatched round-robin over the 8
   // XCDs, so ids with the same id % 8 share an L2.  All subdomains of one
   // row tile get the same XCD, so its slice of T is fetched into that L2.
-  const int nrt = (nout + 63) / 64;
+  const int nrt = (nout + RWS - 1) / RWS;
   const int cnt = gridDim.x / (8 * ((nrt + 7) / 8));
   const int xcd = blockIdx.x & 7, q8 = blockIdx.x >> 3;
   const int rtile = xcd + 8 * (q8 / cnt);
@@ -692,7 +694,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   const int cg = blockIdx.y;                               // 16-column group
   const int c0 = cg * 16;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int rw = wave & 3, kh = wave >> 2;                 // row tile, half of the sum
+  const int rw = wave % RW, kh = wave / RW;                // row tile, part of the sum
   const int op = op_of[s];
   const cpx<T>* Top = Tm + (size_t)op * NI * NI;
   const size_t slot_stride = (size_t)g.nsub * C * NI;
@@ -700,15 +702,15 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   const int jc = lane & 15, kk = lane >> 4, rr = lane & 15;
   const cpx<T> z = mk<T>(T(0), T(0));
   // epilogue operands do not depend on the product: fetch them first
-  StepOut eo[2];
-  cpx<T> ey[2], ein[2], edst[2];
+  StepOut eo[NQ];
+  cpx<T> ey[NQ], ein[NQ], edst[NQ];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     int idx = tid + q * 512;
-    int col = idx >> 6, r = idx & 63;
-    int orow = rtile * 64 + r;
+    int col = idx / RWS, r = idx % RWS;
+    int orow = rtile * RWS + r;
     eo[q] = StepOut{-1, -1, -1};
-    if (orow < nout && c0 + col < C)
+    if (idx < RWS * 16 && orow < nout && c0 + col < C)
       eo[q] = step_out(g, fout, s, orow, c0 + col, C, L, slot_stride, add_y);
     ey[q] = mk<T>(T(0), T(0));
     ein[q] = ey[q];
@@ -718,7 +720,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
     if (eo[q].dst >= 0) edst[q] = slots[eo[q].dst];
   }
   // output dof of this lane's A row
-  const int row = rtile * 64 + rw * 16 + rr;
+  const int row = rtile * RWS + rw * 16 + rr;
   int dout = -1;
   if (row < nout) {
     int q = fs_find(fout, row);
@@ -747,8 +749,8 @@ __global__ __launch_bounds__(512) void k_sweep_step(
       row16[c + 8] = mk<T>(v.im, v.re);
     }
     __syncthreads();
-    // this wave's half of the slices
-    const int hh = (nks + 1) >> 1;
+    // this wave's part of the slices
+    const int hh = (nks + KH - 1) / KH;
     const int ksb = kh * hh, kse = min(nks, ksb + hh);
     const cpx<T>* ap = Top + (size_t)(g.side_off[f] + kb + kk) * NI + (dout >= 0 ? dout : 0);
     const size_t astep = (size_t)4 * NI;
@@ -801,16 +803,17 @@ __global__ __launch_bounds__(512) void k_sweep_step(
     }
   }
   __syncthreads();
-  // add the two halves in a fixed order and stage the 64 x 16 tile
-  T* st = reinterpret_cast<T*>(bp);              // [16][64] complex
-  T* part1 = st + 2 * 16 * 64;                   // second half's partials
+  // add the KH parts in a fixed order and stage the RWS x 16 tile:
+  // part p of the sum at st + p * (2 * 16 * RWS) floats, p = 0 the final tile
+  T* st = reinterpret_cast<T*>(bp);
   const int cc = jc & 7, part = jc >> 3;
-  if (kh == 1) {
+  if (kh > 0) {
+    T* pp = st + (size_t)kh * 2 * 16 * RWS;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       int r = rw * 16 + MF<T>::row(lane, i);
-      part1[2 * (cc * 64 + r) + part] = aR0[i] + aI0[i];
-      part1[2 * ((cc + 8) * 64 + r) + part] = aR1[i] + aI1[i];
+      pp[2 * (cc * RWS + r) + part] = aR0[i] + aI0[i];
+      pp[2 * ((cc + 8) * RWS + r) + part] = aR1[i] + aI1[i];
     }
   }
   __syncthreads();
@@ -818,18 +821,24 @@ __global__ __launch_bounds__(512) void k_sweep_step(
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       int r = rw * 16 + MF<T>::row(lane, i);
-      int i0 = 2 * (cc * 64 + r) + part, i1 = 2 * ((cc + 8) * 64 + r) + part;
-      st[i0] = (aR0[i] + aI0[i]) + part1[i0];
-      st[i1] = (aR1[i] + aI1[i]) + part1[i1];
+      int i0 = 2 * (cc * RWS + r) + part, i1 = 2 * ((cc + 8) * RWS + r) + part;
+      T v0 = aR0[i] + aI0[i], v1 = aR1[i] + aI1[i];
+#pragma unroll
+      for (int p = 1; p < KH; ++p) {
+        v0 += st[(size_t)p * 2 * 16 * RWS + i0];
+        v1 += st[(size_t)p * 2 * 16 * RWS + i1];
+      }
+      st[i0] = v0;
+      st[i1] = v1;
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     if (eo[q].dst < 0) continue;
     int idx = tid + q * 512;
-    int col = idx >> 6, r = idx & 63;
-    cpx<T> v = bp[col * 64 + r] + ey[q];
+    int col = idx / RWS, r = idx % RWS;
+    cpx<T> v = bp[col * RWS + r] + ey[q];
     slots[eo[q].dst] = edst[q] + (v - ein[q]);
   }
 }
@@ -1049,10 +1058,15 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
   const int nsub_chunks = (flen + lcap - 1) / lcap;
   const int LMAX = ((flen + nsub_chunks - 1) / nsub_chunks + 3) / 4 * 4;
   constexpr int KB = sizeof(T) == 4 ? 8 : 4;
-  const int nrt = (nout + 63) / 64;
+  // two 16-row tiles per workgroup, the sum split in four (measured best of
+  // one, two and four tiles at the 1024^2 workload)
+  constexpr int RW = 2;
+  const int nrt = (nout + 16 * RW - 1) / (16 * RW);
   dim3 grid(8 * ((nrt + 7) / 8) * cnt, Cp / 16, 1);
-  size_t lds = std::max<size_t>((size_t)2 * LMAX * 16, 2 * 16 * 64) * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_sweep_step<T, KB>), grid, dim3(512), lds, c->stream,
+  // LDS: the staged operand pairs, or the KH partial tiles of the sum
+  size_t lds = std::max<size_t>((size_t)2 * LMAX * 16, (size_t)(8 / RW) * 16 * 16 * RW) *
+               sizeof(cpx<T>);
+  hipLaunchKernelGGL((k_sweep_step<T, KB, RW>), grid, dim3(512), lds, c->stream,
                      (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_g, (cpx<T>*)c->d_slots,
                      (const cpx<T>*)c->d_y, c->d_op_of_sub, c->d_step_subs + off, L, C, Cp,
                      fin, nin, fout, nout, L == 0 ? 1 : 0, LMAX, nsub_chunks, c->gd);
