@@ -206,7 +206,8 @@ class HipExecutor:
 
 # ------------------------------------------------------------------ server
 class Server:
-    def __init__(self, executor, budget_bytes, tol=1e-10, max_iter=30, keep_results=False):
+    def __init__(self, executor, budget_bytes, tol=1e-10, max_iter=30, keep_results=False,
+                 progress=None):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.tol = tol
@@ -218,6 +219,7 @@ class Server:
         self.created = 0
         self.evictions = 0
         self.steps = 0
+        self.progress = progress      # print a line every `progress` completed requests
 
     # context cache ---------------------------------------------------
     def _evict_one(self):
@@ -341,7 +343,12 @@ class Server:
                 cs = inflight[key]
                 if self.ex.ready(cs.handle):
                     del inflight[key]
-                    finished += self._retire(cs, self.ex.now() - t0)
+                    done = self._retire(cs, self.ex.now() - t0)
+                    if self.progress and done and \
+                            (finished + done) // self.progress > finished // self.progress:
+                        print(f"served {finished + done}/{len(reqs)} requests at "
+                              f"{self.ex.now() - t0:.1f} s", flush=True)
+                    finished += done
                     progressed = True
             if not progressed:
                 self.ex.pause()
@@ -396,14 +403,14 @@ def main(argv=None):
         budget = int(gb * 1e9)
         ex = HipExecutor(cap_max=a.cap, tol=a.tol)
         # capacity: the whole stream at time 0 (closed loop)
-        srv = Server(ex, budget, tol=a.tol)
+        srv = Server(ex, budget, tol=a.tol, progress=50)
         reqs = srv.run(wl.request_stream(a.requests, None, seed=a.seed))
         m = metrics(srv, reqs)
         srv.close()
         cap_rps = m["requests_per_s"]
         print(json.dumps(dict(mode="closed", budget_gb=gb, **m)), flush=True)
         for fr in a.rate_frac:
-            srv = Server(ex, budget, tol=a.tol)
+            srv = Server(ex, budget, tol=a.tol, progress=50)
             reqs = srv.run(wl.request_stream(a.requests, fr * cap_rps, seed=a.seed))
             m = metrics(srv, reqs)
             srv.close()
