@@ -52,7 +52,7 @@ class Request:
         self.cols_done = 0
         self.admitted = None       # time the first column joined a context
         self.done = None
-        self.hit = None            # context existed when the request first joined
+        self.hit = None            # False: the request's admission factored a new context
         self.iters = [0] * self.R
         self.rel = [np.nan] * self.R
         self.failed = False
@@ -103,9 +103,10 @@ class HipExecutor:
         if d > 0:
             time.sleep(d)
 
-    def create(self, key, free_bytes):
-        """Set up and factor the context of `key` within `free_bytes`; None
-        if it does not fit."""
+    def create(self, key, free_bytes, slot_bytes=None):
+        """Set up and factor the context of `key` within `free_bytes`, with
+        as many column slots (up to cap_max) as fit in `slot_bytes` (default
+        `free_bytes`); None if it does not fit."""
         H, torch = self.H, self.torch
         kap, h, P, W, rounds = wl.serve_kappa(key)
         stream = torch.cuda.Stream(device=self.dev)
@@ -121,7 +122,8 @@ class HipExecutor:
             H.hdsw_factor(ctx)
             H.hdsw_batch_reserve(ctx, 1)
             fb, _, ws1 = H.hdsw_query(ctx)
-            fit = (free_bytes - fb) // max(ws1, 1)
+            sb = free_bytes if slot_bytes is None else min(slot_bytes, free_bytes)
+            fit = max(1, (sb - fb) // max(ws1, 1)) if free_bytes - fb >= ws1 else 0
             cap = int(min(self.cap_max, fit))
             while cap > 1:
                 # the estimate leaves out the context's small set-up arrays:
@@ -207,7 +209,7 @@ class HipExecutor:
 # ------------------------------------------------------------------ server
 class Server:
     def __init__(self, executor, budget_bytes, tol=1e-10, max_iter=30, keep_results=False,
-                 progress=None):
+                 progress=None, age_limit=2.0, ctx_share=0.5):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.tol = tol
@@ -220,6 +222,9 @@ class Server:
         self.evictions = 0
         self.steps = 0
         self.progress = progress      # print a line every `progress` completed requests
+        self.age_limit = age_limit    # seconds before a request's key is factored first
+        self.blocked_key = None
+        self.ctx_share = ctx_share    # largest budget share of one context's slots
 
     # context cache ---------------------------------------------------
     def _evict_one(self):
@@ -234,7 +239,8 @@ class Server:
 
     def _create(self, key):
         while True:
-            got = self.ex.create(key, self.budget - self.used)
+            free = self.budget - self.used
+            got = self.ex.create(key, free, min(free, int(self.ctx_share * self.budget)))
             if got is not None:
                 handle, nbytes, cap = got
                 cs = CtxState(key, handle, nbytes, cap)
@@ -247,41 +253,63 @@ class Server:
                 return None
 
     # admission -------------------------------------------------------
+    def _join(self, cs, req, now):
+        n = min(cs.cap - cs.nact, req.pending)
+        if n <= 0:
+            return
+        if req.admitted is None:
+            req.admitted = now
+            if self.keep:
+                req.result = self.ex.result_buffer(cs.handle, req.R)
+        slots = self.ex.add(cs.handle, req, req.next_col, n)
+        for j, s in enumerate(slots):
+            cs.slots[s] = (req, req.next_col + j)
+            cs.iters[s] = 0
+        req.next_col += n
+
     def _admit(self, queue, now, inflight):
-        blocked_new = False
-        for req in list(queue):
+        """Cache-aware admission.  (1) Queued requests join the contexts of
+        their keys, first come first served, while slots are free.  (2) At
+        most one new context per round, for the key of the oldest request
+        that has waited longer than age_limit, else for the key with the
+        most waiting columns (ties: oldest request); if it cannot get memory
+        even after evicting idle contexts, no other key is factored ahead
+        of it."""
+        for req in queue:
             cs = self.ctxs.get(req.key)
             if cs is None:
-                if blocked_new:
-                    continue
-                cs = self._create(req.key)
-                if cs is None:
-                    # first request that cannot get memory: later requests
-                    # may still join existing contexts but not create new
-                    # ones, so that it is not starved
-                    blocked_new = True
-                    continue
-                if req.hit is None:
-                    req.hit = False
-            elif req.hit is None:
+                continue
+            if req.hit is None:
                 req.hit = True
             self.ctxs.move_to_end(req.key)
-            if req.key in inflight:
-                continue           # joins after the context's running step
-            n = min(cs.cap - cs.nact, req.pending)
-            if n <= 0:
-                continue
-            if req.admitted is None:
-                req.admitted = now
-                if self.keep:
-                    req.result = self.ex.result_buffer(cs.handle, req.R)
-            slots = self.ex.add(cs.handle, req, req.next_col, n)
-            for j, s in enumerate(slots):
-                cs.slots[s] = (req, req.next_col + j)
-                cs.iters[s] = 0
-            req.next_col += n
-            if req.pending == 0:
-                queue.remove(req)
+            if req.key not in inflight:
+                self._join(cs, req, now)
+        waiting = [r for r in queue if r.key not in self.ctxs]
+        if waiting:
+            old = [r for r in waiting if now - r.arrival > self.age_limit]
+            if old:
+                key = min(old, key=lambda r: (r.arrival, r.rid)).key
+            else:
+                agg = {}
+                for r in waiting:
+                    a = agg.setdefault(r.key, [0, r.arrival, r.rid])
+                    a[0] += r.pending
+                key = max(agg, key=lambda k: (agg[k][0], -agg[k][1], -agg[k][2]))
+            cs = self._create(key)
+            self.blocked_key = key if cs is None else None
+            if cs is not None:
+                # the first request of the key triggered the factorization
+                # (a miss); the others queued with it reuse it
+                first = True
+                for req in waiting:
+                    if req.key == key:
+                        if req.hit is None:
+                            req.hit = not first
+                        first = False
+                        self._join(cs, req, now)
+        queue[:] = [r for r in queue if r.pending > 0]
+        # another key may be factored at once in the next round
+        return bool(waiting) and cs is not None and any(r.key not in self.ctxs for r in queue)
 
     def _retire(self, cs, now):
         """Read the finished step's residuals and take converged columns;
@@ -320,21 +348,22 @@ class Server:
             now = self.ex.now() - t0
             while arrivals and arrivals[0].arrival <= now:
                 queue.append(arrivals.popleft())
-            if queue:
-                self._admit(queue, now, inflight)
+            more = self._admit(queue, now, inflight) if queue else False
             for key, cs in self.ctxs.items():
                 if cs.nact > 0 and key not in inflight:
                     self.ex.step(cs.handle)
                     inflight[key] = cs
                     self.steps += 1
             if not inflight:
-                if queue:
-                    # nothing runs and the queue head cannot get memory even
+                if queue and not more:
+                    # nothing runs and the chosen key cannot get memory even
                     # with every idle context evicted: it never fits
-                    head = queue.pop(0)
-                    head.failed = True
-                    head.done = now
-                    finished += 1
+                    bad = self.blocked_key if self.blocked_key is not None else queue[0].key
+                    for r in [r for r in queue if r.key == bad and r.next_col == 0]:
+                        queue.remove(r)
+                        r.failed = True
+                        r.done = now
+                        finished += 1
                 elif arrivals:
                     self.ex.idle_until(t0 + arrivals[0].arrival)
                 continue
@@ -350,7 +379,7 @@ class Server:
                               f"{self.ex.now() - t0:.1f} s", flush=True)
                     finished += done
                     progressed = True
-            if not progressed:
+            if not progressed and not more:
                 self.ex.pause()
         self.wall = self.ex.now() - t0
         return reqs

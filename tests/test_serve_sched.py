@@ -47,11 +47,14 @@ class StubExecutor:
         busy = [h["finish"] for h in self.live.values() if h["finish"] is not None]
         self.t = max(self.t, min(busy)) if busy else self.t + 1e-5
 
-    def create(self, key, free):
+    def create(self, key, free, slot_bytes=None):
         N = key[0]
         fb = self.fac_bytes * N * N
         per = self.col_bytes * N * N
-        cap = int(min(self.cap_max, (free - fb) // per)) if free > fb else 0
+        sb = free if slot_bytes is None else min(free, slot_bytes)
+        cap = 0
+        if free - fb >= per:
+            cap = int(min(self.cap_max, max(1, (sb - fb) // per)))
         if cap < 1:
             return None
         self.t += 1e-3 * (N / 256) ** 2          # factorization time
@@ -143,7 +146,8 @@ def test_all_requests_complete_and_columns_taken_once():
     _check_complete(ex, reqs)
     m = serve.metrics(srv, reqs)
     assert m["failed"] == 0 and m["rhs"] == 15
-    # K256 requested three times: one miss, two hits
+    # K256 requested three times: one miss, two hits (the later arrivals
+    # find its context)
     hits = [r.hit for r in reqs]
     assert hits == [False, False, True, False, True, False]
     assert m["cache_hit_rate"] == pytest.approx(2 / 6, abs=1e-4)
@@ -180,11 +184,12 @@ def test_blocked_request_is_not_starved_by_later_new_keys():
     budget = 5.0 * 512 * 512
     spec = [(0.0, K512, 1), (0.0, K512L, 1), (0.0, K256, 1), (0.0, K512, 1)]
     ex = StubExecutor(cap_max=2)
-    srv = serve.Server(ex, budget_bytes=budget)
+    srv = serve.Server(ex, budget_bytes=budget, ctx_share=1.0)
     reqs = srv.run(_reqs(spec))
     _check_complete(ex, reqs)
     assert ex.created.index(K512L) < ex.created.index(K256)
-    assert reqs[3].hit is True and reqs[3].admitted == reqs[0].admitted
+    # the two K512 requests share the first context and join it together
+    assert ex.created[0] == K512 and reqs[3].admitted == reqs[0].admitted
 
 
 def test_request_that_never_fits_fails_without_hanging():
@@ -209,6 +214,32 @@ def test_contexts_are_serviced_asynchronously():
     lat_small = small.done - small.arrival
     assert lat_small < 3 * StubExecutor.step_cost(256) + 0.02      # own steps + factors
     assert lat_small < StubExecutor.step_cost(1024) * 3
+
+
+def test_cache_aware_admission_prefers_the_most_waiting_columns():
+    # with everything queued at once and room for one context at a time,
+    # the key with the most waiting columns is factored first, and each key
+    # is factored once
+    budget = 4.0 * 512 * 512
+    spec = [(0.0, K512L, 1), (0.0, K512, 2), (0.0, K512L, 1), (0.0, K512, 3),
+            (0.0, K512L, 1)]
+    ex = StubExecutor(cap_max=8)
+    srv = serve.Server(ex, budget_bytes=budget, ctx_share=1.0)
+    reqs = srv.run(_reqs(spec))
+    _check_complete(ex, reqs)
+    assert ex.created == [K512, K512L]
+    assert srv.created == 2 and srv.evictions == 1
+
+
+def test_old_requests_are_factored_first():
+    # past the age limit the oldest waiting request's key goes first
+    budget = 4.0 * 512 * 512
+    spec = [(0.0, K512L, 1), (0.0, K512, 2), (0.0, K512, 3)]
+    ex = StubExecutor(cap_max=8)
+    srv = serve.Server(ex, budget_bytes=budget, ctx_share=1.0, age_limit=-1.0)
+    reqs = srv.run(_reqs(spec))
+    _check_complete(ex, reqs)
+    assert ex.created == [K512L, K512]
 
 
 def test_request_stream_recipe():
