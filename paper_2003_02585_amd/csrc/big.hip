@@ -209,6 +209,117 @@ int gemm_bk() {
   return sizeof(T) == 4 ? 32 : 16;
 }
 
+// Skinny product (at most 8 columns per group), HBM-bound: each wave
+// streams a 16-row strip of A straight from memory into the MFMA operand
+// registers, a batch of SB 4-deep slices ahead of the multiplication; B is
+// staged in LDS in chunks of KC rows shared by the workgroup's 4 waves.
+constexpr int SK_KC = 256, SK_SB = 16;
+
+template <class T, bool TILED>
+__global__ __launch_bounds__(256) void k_cgemm_skinny(GemmArgs a, int nrt) {
+  typedef typename MF<T>::v4 v4;
+  __shared__ cpx<T> Bs[2][SK_KC][8];          // [buf][k][column]
+  __shared__ cpx<T> Cs[8][GM];
+  const int z = blockIdx.y;
+  const int xcd = blockIdx.x & 7, pos = blockIdx.x >> 3;
+  const int rtile = xcd + 8 * pos;
+  if (rtile >= nrt) return;
+  const int ncols = a.grp_cnt ? a.grp_cnt[z] * a.cpb : a.N;
+  if (ncols <= 0) return;
+  const int row0 = rtile * GM;
+  const int opz = a.grp_op ? a.grp_op[z] : z;
+  const int off = a.grp_off ? a.grp_off[z] : 0;
+  const cpx<T>* A = reinterpret_cast<const cpx<T>*>(a.A) + (long long)opz * a.sAz;
+  const cpx<T>* B = reinterpret_cast<const cpx<T>*>(a.B) + (long long)z * a.sBz;
+  cpx<T>* C = reinterpret_cast<cpx<T>*>(a.C) + (long long)z * a.sCz;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // this lane's A operand: row r, k = 4 s + kq
+  const int r = row0 + wave * 16 + (lane & 15), kq = lane >> 4;
+  const bool rok = r < a.M;
+  const cpx<T>* arow = nullptr;
+  if (!TILED) arow = A + (rok ? (a.arow ? a.arow[r] : r) : 0);
+  const cpx<T>* atile = TILED ? A + (long long)a.a_rt[rtile] * a.a_tile_ld * (GM * 32) : nullptr;
+  const int rt_in = wave * 16 + (lane & 15);
+  // B columns of this group (thread c < 8 of each staging pass)
+  const int mc = lane & 15, cc = mc & 7;
+  const bool hi = mc >= 8;
+  v4 accR = v4{T(0), T(0), T(0), T(0)}, accI = accR;
+  const int nkc = (a.Kd + SK_KC - 1) / SK_KC;
+  auto stageB = [&](int kc, int buf) {
+    const int k0 = kc * SK_KC;
+    for (int idx = tid; idx < SK_KC * 8; idx += 256) {
+      const int j = idx / SK_KC, kk = idx - j * SK_KC;   // consecutive threads: consecutive k
+      const int k = k0 + kk;
+      cpx<T> v;
+      v.re = T(0);
+      v.im = T(0);
+      if (j < ncols && k < a.Kd) {
+        const int e = j / a.cpb, jj = j - e * a.cpb;
+        const int eid = a.ids ? a.ids[off + e] : e;
+        v = B[(long long)eid * a.sb + (long long)jj * a.ldb + k];
+      }
+      Bs[buf][kk][j] = v;
+    }
+  };
+  stageB(0, 0);
+  __syncthreads();
+  for (int kc = 0; kc < nkc; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nkc) stageB(kc + 1, buf ^ 1);
+    const int k0 = kc * SK_KC;
+    const int ns = min(SK_KC, a.Kd - k0 + 3) / 4;          // slices in this chunk
+    cpx<T> av[SK_SB];
+    for (int s0 = 0; s0 < ns; s0 += SK_SB) {
+#pragma unroll
+      for (int u = 0; u < SK_SB; ++u) {
+        const int k = k0 + 4 * (s0 + u) + kq;
+        av[u].re = T(0);
+        av[u].im = T(0);
+        if (rok && s0 + u < ns && k < a.Kd) {
+          if (TILED)
+            av[u] = atile[(long long)a.a_kt[k >> 5] * (GM * 32) + (k & 31) * GM + rt_in];
+          else
+            av[u] = arow[gemm_acol(a, k) * a.lda];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SK_SB; ++u) {
+        if (s0 + u >= ns) break;
+        const cpx<T> v = Bs[buf][4 * (s0 + u) + kq][cc];
+        const T p_re = hi ? v.im : v.re;
+        const T p_im = hi ? v.re : -v.im;
+        accR = MF<T>::mfma(av[u].re, p_re, accR);
+        accI = MF<T>::mfma(av[u].im, p_im, accI);
+      }
+    }
+    __syncthreads();
+  }
+  T* cs = reinterpret_cast<T*>(&Cs[0][0]);
+  const int part = mc >> 3;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rr = wave * 16 + MF<T>::row(lane, i);
+    cs[2 * (cc * GM + rr) + part] = accR[i] + accI[i];
+  }
+  __syncthreads();
+  const int orow = tid & 63, oc = tid >> 6;
+  if (row0 + orow >= a.M) return;
+  const int crow = a.c_row ? a.c_row[row0 + orow] : row0 + orow;
+  if (crow < 0) return;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int c = oc * 2 + q;
+    if (c >= ncols) break;
+    const int e = c / a.cpb, jj = c - e * a.cpb;
+    const int eid = a.ids ? a.ids[off + e] : e;
+    cpx<T>* dst = C + (long long)eid * a.sc + (long long)jj * a.ldc + crow;
+    cpx<T> v = Cs[c][orow];
+    if (a.neg) v = -v;
+    if (a.beta) v = *dst + v;
+    *dst = v;
+  }
+}
+
 // C = beta C + s (sum of the partial products), in a fixed order
 template <class T>
 __global__ void k_gemm_combine(GemmArgs a, int ngroups, int maxcols) {
@@ -248,6 +359,17 @@ hipError_t gemm(hipStream_t st, const GemmArgs& a_in, int maxcols, int ngroups) 
   a.part_cols = maxcols;
   constexpr int BK = sizeof(T) == 4 ? 32 : 16;
   const int nrt = (a.M + GM - 1) / GM, nct = (maxcols + GN - 1) / GN;
+  // at most 8 columns per group: the product streams A (HBM-bound)
+  if (maxcols <= 8 && a.ksplit == 1 && (!a.a_rt || BK == 32)) {
+    dim3 g2(8 * ((nrt + 7) / 8), ngroups, 1);
+    if (a.a_rt) {
+      if (a.M % GM != 0) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_cgemm_skinny<T, true>), g2, dim3(256), 0, st, a, nrt);
+    } else {
+      hipLaunchKernelGGL((k_cgemm_skinny<T, false>), g2, dim3(256), 0, st, a, nrt);
+    }
+    return hipGetLastError();
+  }
   dim3 grid(8 * ((nrt + 7) / 8) * nct, 1, ngroups * a.ksplit);
   if (a.a_rt) {
     // tiled A: whole tiles only
