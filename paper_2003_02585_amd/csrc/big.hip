@@ -35,16 +35,6 @@ namespace hdsw {
 // columns.
 constexpr int GM = 64, GN = 32, GPAD = 80;
 
-// column k of A: k itself, or the column given by the segment map
-__device__ __forceinline__ long long gemm_acol(const GemmArgs& a, int k) {
-  if (a.nseg == 0) return k;
-  int s = 0;
-#pragma unroll
-  for (int q = 1; q < 6; ++q)
-    if (q < a.nseg && k >= a.seg_k0[q]) s = q;
-  return (long long)a.seg_c0[s] + (k - a.seg_k0[s]);
-}
-
 // BK-deep chunks of the sum, double-buffered in LDS (one barrier per
 // chunk): the next chunk's global loads are in flight while the current one
 // is multiplied.
@@ -89,7 +79,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
   // A: row ar, k = ak .. ak + AL - 1
   const int ar = tid & 63, ak = (tid >> 6) * AL;
   const bool arow_ok = row0 + ar < a.M;
-  const cpx<T>* acol = A + (arow_ok ? (a.arow ? a.arow[row0 + ar] : row0 + ar) : 0);
+  const cpx<T>* acol = A + (arow_ok ? row0 + ar : 0);
   const cpx<T>* atile = TILED ? A + (long long)a.a_rt[rtile] * a.a_tile_ld * (GM * BK) : nullptr;
 
   cpx<T> ra[AL], rb[BL];
@@ -114,7 +104,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
         int k = (k0) + ak + u;                                                   \
         ra[u].re = T(0);                                                         \
         ra[u].im = T(0);                                                         \
-        if (arow_ok && k < a.Kd) ra[u] = acol[gemm_acol(a, k) * a.lda];          \
+        if (arow_ok && k < a.Kd) ra[u] = acol[(long long)k * a.lda];             \
       }                                                                          \
     }                                                                            \
     _Pragma("unroll") for (int u = 0; u < BL; ++u) {                             \
@@ -236,8 +226,7 @@ __global__ __launch_bounds__(256) void k_cgemm_skinny(GemmArgs a, int nrt) {
   // this lane's A operand: row r, k = 4 s + kq
   const int r = row0 + wave * 16 + (lane & 15), kq = lane >> 4;
   const bool rok = r < a.M;
-  const cpx<T>* arow = nullptr;
-  if (!TILED) arow = A + (rok ? (a.arow ? a.arow[r] : r) : 0);
+  const cpx<T>* arow = TILED ? nullptr : A + (rok ? r : 0);
   const cpx<T>* atile = TILED ? A + (long long)a.a_rt[rtile] * a.a_tile_ld * (GM * 32) : nullptr;
   const int rt_in = wave * 16 + (lane & 15);
   // B columns of this group (thread c < 8 of each staging pass)
@@ -279,7 +268,7 @@ __global__ __launch_bounds__(256) void k_cgemm_skinny(GemmArgs a, int nrt) {
           if (TILED)
             av[u] = atile[(long long)a.a_kt[k >> 5] * (GM * 32) + (k & 31) * GM + rt_in];
           else
-            av[u] = arow[gemm_acol(a, k) * a.lda];
+            av[u] = arow[(long long)k * a.lda];
         }
       }
 #pragma unroll

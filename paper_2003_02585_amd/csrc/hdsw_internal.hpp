@@ -261,12 +261,6 @@ struct GemmArgs {
   const int* grp_cnt;
   int neg;
   int beta;
-  const int* arow;   // row r of A is row arow[r] of the stored matrix (nullable)
-  // column k of A: seg_c0[s] + (k - seg_k0[s]) for the segment s holding k
-  // (seg_k0 increasing, seg_k0[0] = 0), or k itself when nseg = 0
-  int nseg;
-  int seg_k0[6];
-  int seg_c0[6];
   // tiled A (64-row x BK-deep tiles stored contiguously, k-major inside a
   // tile): row tile of workgroup x = a_rt[x], chunk ch = tile a_kt[ch], tile
   // (rt, kt) at A + (rt * a_tile_ld + kt) * 64 * BK; null = plain layout

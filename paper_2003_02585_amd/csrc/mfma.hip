@@ -700,7 +700,6 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   const size_t slot_stride = (size_t)g.nsub * C * NI;
   const cpx<T>* gsrc = gbuf + (size_t)s * Cp * NI;
   const int jc = lane & 15, kk = lane >> 4, rr = lane & 15;
-  const cpx<T> z = mk<T>(T(0), T(0));
   // epilogue operands do not depend on the product: fetch them first
   StepOut eo[NQ];
   cpx<T> ey[NQ], ein[NQ], edst[NQ];

@@ -57,3 +57,27 @@ def test_setup_rejects_invalid_arguments(bad):
     with pytest.raises(H.HdswError) as ei:
         H.hdsw_setup(kap, 1.0 / N, (bad.get("P", 2),) * 2, bad.get("W", 8), opt)
     assert ei.value.status == H.HDSW_EINVAL
+
+
+@pytest.mark.parametrize("bad", [
+    dict(N=(12, 12, 13), P=(2, 2, 2)),    # an axis not divisible by its subdomains
+    dict(N=(12, 12, 12), P=(2, 2, 12)),   # one node per subdomain on an axis
+    dict(W=0),
+    dict(rounds=5),
+])
+def test_setup_rejects_invalid_3d_arguments(bad):
+    from paper_2003_02585_amd import hdsw as H
+    N = bad.get("N", (12, 12, 12))
+    kap = np.full(tuple(reversed(N)), 40.0)
+    opt = H.hdsw_default_options(rounds=bad.get("rounds", 1))
+    with pytest.raises(H.HdswError) as ei:
+        H.hdsw_setup(kap, 1.0 / N[0], bad.get("P", (2, 2, 2)), bad.get("W", 3), opt)
+    assert ei.value.status == H.HDSW_EINVAL
+
+
+def test_setup_rejects_four_dimensions():
+    from paper_2003_02585_amd import hdsw as H
+    kap = np.full((4, 4, 4, 4), 40.0)
+    with pytest.raises(H.HdswError) as ei:
+        H.hdsw_setup(kap, 0.25, (2, 2, 2), 1, H.hdsw_default_options())
+    assert ei.value.status == H.HDSW_EINVAL
