@@ -94,6 +94,7 @@ class HipExecutor:
         self.add_chunk = add_chunk
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self._sink = None
+        self._pool = None
 
     def now(self):
         return time.perf_counter()
@@ -103,10 +104,12 @@ class HipExecutor:
         if d > 0:
             time.sleep(d)
 
-    def create(self, key, free_bytes, slot_bytes=None):
-        """Set up and factor the context of `key` within `free_bytes`, with
-        as many column slots (up to cap_max) as fit in `slot_bytes` (default
-        `free_bytes`); None if it does not fit."""
+    def start_create(self, key, free_bytes, slot_bytes=None):
+        """Set up the context of `key` within `free_bytes` (host work and the
+        factor storage, on the calling thread) and start its factorization
+        and slot reservation on a worker thread, on the context's own
+        stream, so that other contexts keep running meanwhile.  Returns a
+        token for poll_create, or None if the factors do not fit."""
         H, torch = self.H, self.torch
         kap, h, P, W, rounds = wl.serve_kappa(key)
         stream = torch.cuda.Stream(device=self.dev)
@@ -118,6 +121,14 @@ class HipExecutor:
             if e.status == H.HDSW_ENOMEM:
                 return None
             raise
+        if self._pool is None:
+            import concurrent.futures
+            self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=1)
+        fut = self._pool.submit(self._factor_reserve, ctx, free_bytes, slot_bytes)
+        return dict(fut=fut, handle=dict(ctx=ctx, stream=stream, N=kap.shape[-1], h=h))
+
+    def _factor_reserve(self, ctx, free_bytes, slot_bytes):
+        H = self.H
         try:
             H.hdsw_factor(ctx)
             H.hdsw_batch_reserve(ctx, 1)
@@ -140,12 +151,22 @@ class HipExecutor:
             if cap == 1:
                 H.hdsw_batch_reserve(ctx, 1)
             fb, _, ws = H.hdsw_query(ctx)
+            return int(fb + ws), cap
         except H.HdswError as e:
             H.hdsw_destroy(ctx)
             if e.status == H.HDSW_ENOMEM:
                 return None
             raise
-        return dict(ctx=ctx, stream=stream, N=kap.shape[-1], h=h), int(fb + ws), cap
+
+    def poll_create(self, tok):
+        """None while the factorization runs; then (handle, bytes, capacity),
+        or False if it did not fit."""
+        if not tok["fut"].done():
+            return None
+        r = tok["fut"].result()
+        if r is None:
+            return False
+        return tok["handle"], r[0], r[1]
 
     def sources(self, N, h, positions):
         """The request's input: Gaussian point sources (sigma = 2h) at the
@@ -224,6 +245,8 @@ class Server:
         self.progress = progress      # print a line every `progress` completed requests
         self.age_limit = age_limit    # seconds before a request's key is factored first
         self.blocked_key = None
+        self.pending = None           # (key, token, bytes held) of the running factorization
+        self.ctxs_first = {}          # key -> hit flag of its first request (a miss)
         self.ctx_share = ctx_share    # largest budget share of one context's slots
 
     # context cache ---------------------------------------------------
@@ -237,20 +260,41 @@ class Server:
                 return True
         return False
 
-    def _create(self, key):
+    def _start_create(self, key):
+        """Start factoring `key`, evicting idle contexts (least recently
+        used first) until its factors fit; the whole free budget is held
+        for it until it is done."""
         while True:
             free = self.budget - self.used
-            got = self.ex.create(key, free, min(free, int(self.ctx_share * self.budget)))
-            if got is not None:
-                handle, nbytes, cap = got
-                cs = CtxState(key, handle, nbytes, cap)
-                self.ctxs[key] = cs
-                self.used += nbytes
-                self.peak = max(self.peak, self.used)
-                self.created += 1
-                return cs
+            tok = self.ex.start_create(key, free, min(free, int(self.ctx_share * self.budget)))
+            if tok is not None:
+                self.pending = (key, tok, free)
+                self.used += free
+                return True
             if not self._evict_one():
-                return None
+                return False
+
+    def _finish_create(self, now):
+        """Poll the pending factorization; returns True if it ended."""
+        key, tok, held = self.pending
+        r = self.ex.poll_create(tok)
+        if r is None:
+            return False
+        self.pending = None
+        self.used -= held
+        if r is False:
+            # the factorization's own workspaces did not fit: free an idle
+            # context and try again, or give up on the key
+            if not self._evict_one():
+                self.blocked_key = key
+            return True
+        handle, nbytes, cap = r
+        cs = CtxState(key, handle, nbytes, cap)
+        self.ctxs[key] = cs
+        self.used += nbytes
+        self.peak = max(self.peak, self.used)
+        self.created += 1
+        return True
 
     # admission -------------------------------------------------------
     def _join(self, cs, req, now):
@@ -269,23 +313,27 @@ class Server:
 
     def _admit(self, queue, now, inflight):
         """Cache-aware admission.  (1) Queued requests join the contexts of
-        their keys, first come first served, while slots are free.  (2) At
-        most one new context per round, for the key of the oldest request
-        that has waited longer than age_limit, else for the key with the
-        most waiting columns (ties: oldest request); if it cannot get memory
-        even after evicting idle contexts, no other key is factored ahead
-        of it."""
+        their keys, first come first served, while slots are free.  (2) One
+        factorization at a time runs beside the other contexts' iterations:
+        for the key of the oldest request that has waited longer than
+        age_limit, else for the key with the most waiting columns (ties:
+        oldest request).  Returns True while a factorization is pending."""
+        if self.pending is not None:
+            self._finish_create(now)
         for req in queue:
             cs = self.ctxs.get(req.key)
             if cs is None:
                 continue
             if req.hit is None:
-                req.hit = True
+                # the first request of a new key triggered its
+                # factorization (a miss); later ones reuse it
+                req.hit = self.ctxs_first.pop(req.key, True)
             self.ctxs.move_to_end(req.key)
             if req.key not in inflight:
                 self._join(cs, req, now)
+        queue[:] = [r for r in queue if r.pending > 0]
         waiting = [r for r in queue if r.key not in self.ctxs]
-        if waiting:
+        if self.pending is None and waiting:
             old = [r for r in waiting if now - r.arrival > self.age_limit]
             if old:
                 key = min(old, key=lambda r: (r.arrival, r.rid)).key
@@ -295,21 +343,12 @@ class Server:
                     a = agg.setdefault(r.key, [0, r.arrival, r.rid])
                     a[0] += r.pending
                 key = max(agg, key=lambda k: (agg[k][0], -agg[k][1], -agg[k][2]))
-            cs = self._create(key)
-            self.blocked_key = key if cs is None else None
-            if cs is not None:
-                # the first request of the key triggered the factorization
-                # (a miss); the others queued with it reuse it
-                first = True
-                for req in waiting:
-                    if req.key == key:
-                        if req.hit is None:
-                            req.hit = not first
-                        first = False
-                        self._join(cs, req, now)
-        queue[:] = [r for r in queue if r.pending > 0]
-        # another key may be factored at once in the next round
-        return bool(waiting) and cs is not None and any(r.key not in self.ctxs for r in queue)
+            if self._start_create(key):
+                self.blocked_key = None
+                self.ctxs_first[key] = False
+            else:
+                self.blocked_key = key
+        return self.pending is not None
 
     def _retire(self, cs, now):
         """Read the finished step's residuals and take converged columns;
@@ -355,7 +394,9 @@ class Server:
                     inflight[key] = cs
                     self.steps += 1
             if not inflight:
-                if queue and not more:
+                if more:
+                    self.ex.pause()          # a factorization is running
+                elif queue:
                     # nothing runs and the chosen key cannot get memory even
                     # with every idle context evicted: it never fits
                     bad = self.blocked_key if self.blocked_key is not None else queue[0].key
@@ -379,12 +420,19 @@ class Server:
                               f"{self.ex.now() - t0:.1f} s", flush=True)
                     finished += done
                     progressed = True
-            if not progressed and not more:
+            if not progressed:
                 self.ex.pause()
         self.wall = self.ex.now() - t0
         return reqs
 
     def close(self):
+        if self.pending is not None:
+            while self.ex.poll_create(self.pending[1]) is None:
+                self.ex.pause()
+            r = self.ex.poll_create(self.pending[1])
+            if r:
+                self.ex.destroy(r[0])
+            self.pending = None
         for cs in self.ctxs.values():
             self.ex.destroy(cs.handle)
         self.ctxs.clear()

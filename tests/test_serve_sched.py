@@ -26,6 +26,7 @@ class StubExecutor:
         self.taken = []
         self.adds = []
         self.created = []
+        self.pending = []
         self.max_concurrent_steps = 0
 
     # model
@@ -45,9 +46,12 @@ class StubExecutor:
 
     def pause(self):
         busy = [h["finish"] for h in self.live.values() if h["finish"] is not None]
+        busy += [tok["ready"] for tok in self.pending]
         self.t = max(self.t, min(busy)) if busy else self.t + 1e-5
 
-    def create(self, key, free, slot_bytes=None):
+    def start_create(self, key, free, slot_bytes=None):
+        # factors must fit at set-up; the factorization then runs in the
+        # background for factor_cost(N) of virtual time
         N = key[0]
         fb = self.fac_bytes * N * N
         per = self.col_bytes * N * N
@@ -57,13 +61,24 @@ class StubExecutor:
             cap = int(min(self.cap_max, max(1, (sb - fb) // per)))
         if cap < 1:
             return None
-        self.t += 1e-3 * (N / 256) ** 2          # factorization time
-        hid = self.next_id
-        self.next_id += 1
-        h = dict(id=hid, key=key, cap=cap, slots={}, finish=None, stepped=set())
-        self.live[hid] = h
+        assert not self.pending, "one factorization at a time"
+        tok = dict(key=key, cap=cap, nbytes=int(fb + cap * per),
+                   ready=self.t + 1e-3 * (N / 256) ** 2)
+        self.pending.append(tok)
         self.created.append(key)
-        return h, int(fb + cap * per), cap
+        return tok
+
+    def poll_create(self, tok):
+        if self.t < tok["ready"]:
+            return None
+        if tok in self.pending:
+            self.pending.remove(tok)
+            hid = self.next_id
+            self.next_id += 1
+            tok["h"] = dict(id=hid, key=tok["key"], cap=tok["cap"], slots={}, finish=None,
+                            stepped=set())
+            self.live[hid] = tok["h"]
+        return tok["h"], tok["nbytes"], tok["cap"]
 
     def add(self, h, req, c0, n):
         free = [s for s in range(h["cap"]) if s not in h["slots"]]
@@ -273,3 +288,18 @@ def test_stub_sources_match_workload_sources():
     gy = wl.gaussian_axis(N, h, p[1], 2 * h)
     f = (gx[None, :] * gy[:, None]) / wl.gaussian_mass(2, 2 * h)
     assert np.array_equal(f, wl.gaussian_source((N, N), h, p, 2 * h))
+
+
+def test_factorization_runs_beside_other_contexts():
+    # a large key is factored while a small key's iterations go on: the
+    # small request finishes long before the large factorization ends
+    K2048 = (2048, 128, None, 10)
+    spec = [(0.0, K512, 1), (0.0005, K2048, 1)]
+    ex = StubExecutor(cap_max=4)
+    srv = serve.Server(ex, budget_bytes=1e9)
+    reqs = srv.run(_reqs(spec))
+    _check_complete(ex, reqs)
+    small, big = reqs
+    factor_big = 1e-3 * (2048 / 256) ** 2
+    assert small.done < 0.02 < factor_big
+    assert big.done > factor_big
