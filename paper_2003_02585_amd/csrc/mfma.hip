@@ -546,9 +546,218 @@ __global__ __launch_bounds__(1024) void k_factor_step(cpx<T>* X, size_t xstride,
   }
 }
 
+// Register-resident variant for blocks of n <= 32 B: a 32 x 32 grid of
+// threads, thread (tr, tc) = (tid % 32, tid / 32) holding the B x B
+// sub-block of rows B tr.., columns B tc.. in registers (zero beyond n).
+// Per pivot: the search in column j and the interchanged column j are
+// formed within the 32 threads of column group j / B (one half-wave,
+// shuffles), the old rows j and p go through LDS (buffers double-buffered
+// by pivot parity, so two barriers per pivot), and every thread updates
+// its own sub-block.  Same
+// arithmetic and pivot rule as k_factor_step.  Register arrays are indexed
+// by unrolled compile-time loops only (a run-time index would spill them).
+template <class T, int B>
+__global__ __launch_bounds__(1024) void k_factor_reg(cpx<T>* X, size_t xstride,
+                                                     const cpx<T>* coefT, size_t cstride,
+                                                     GeoDev g, int step, int middle, int* flag,
+                                                     int nops) {
+  constexpr int NB = 32 * B;
+  __shared__ cpx<T> rowj[2][NB], rowp[2][NB], colv[2][NB];
+  __shared__ int pivs[2];
+  __shared__ int perm[NB];
+  __shared__ int place[NB];
+  __shared__ int src[NB];
+  const int op = blockIdx.x, half = blockIdx.y;
+  if (op >= nops) return;
+  const int n = g.n, nP = g.nP, K = g.K, mid = g.mid;
+  int k, pa = -1, fa = 0, pb2 = -1, fb = 0;
+  if (middle) {
+    if (half) return;
+    k = mid;
+    pa = mid - 1;
+    fa = mid;
+    pb2 = mid + 1;
+    fb = mid + 1;
+  } else if (half == 0) {
+    k = step;
+    if (k >= mid) return;
+    if (k > 0) { pa = k - 1; fa = k; }
+  } else {
+    k = K - 1 - step;
+    if (k <= mid) return;
+    if (k < K - 1) { pa = k + 1; fa = k + 1; }
+  }
+  const int tid = threadIdx.x, tr = tid & 31, tc = tid >> 5;
+  const int r0 = B * tr, c0 = B * tc;
+  const cpx<T>* Xo = X + (size_t)op * xstride;
+  cpx<T>* M = X + (size_t)op * xstride + (size_t)k * nP * nP;
+  const cpx<T>* co = coefT + (size_t)op * cstride;
+  const cpx<T>* ax = co + (size_t)k * (n + 1);
+  const cpx<T>* ay = co + (size_t)K * (n + 1);
+  const cpx<T>* dg = co + (size_t)K * (n + 1) + (size_t)(K + 1) * n + (size_t)k * n;
+  const cpx<T>* PA = pa >= 0 ? Xo + (size_t)pa * nP * nP : nullptr;
+  const cpx<T>* PB = pb2 >= 0 ? Xo + (size_t)pb2 * nP * nP : nullptr;
+  cpx<T> m[B][B];
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int i = r0 + a, j = c0 + b;
+      cpx<T> v = mk<T>(T(0), T(0));
+      if (i < n && j < n) {
+        if (i == j) v = dg[i];
+        else if (j == i + 1) v = ax[j];
+        else if (i == j + 1) v = ax[i];
+        const size_t idx = (size_t)i * nP + j;
+        if (PA) v = v - ay[(size_t)fa * n + i] * ay[(size_t)fa * n + j] * PA[idx];
+        if (PB) v = v - ay[(size_t)fb * n + i] * ay[(size_t)fb * n + j] * PB[idx];
+      }
+      m[a][b] = v;
+    }
+  for (int j = 0; j < n; ++j) {
+    const int par = j & 1;
+    // 1. column group j / B: pivot search (largest |Re| + |Im| at or below
+    //    the diagonal, lowest row on ties) and column j after the
+    //    interchange of rows j and p, both within the half-wave
+    if (tc == j / B) {
+      T best = T(-1);
+      int bi = n;
+      cpx<T> cj[B];
+#pragma unroll
+      for (int a = 0; a < B; ++a) {
+        cj[a] = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+          if (c0 + b == j) {
+            cj[a] = m[a][b];
+            if (r0 + a >= j && r0 + a < n) {
+              const T v = fabs(m[a][b].re) + fabs(m[a][b].im);
+              if (v > best) { best = v; bi = r0 + a; }
+            }
+          }
+      }
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) {
+        const T ob = __shfl_xor(best, o, 32);
+        const int oi = __shfl_xor(bi, o, 32);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      const int p = bi < n ? bi : j;
+      // entries (j, j) and (p, j) from the threads holding rows j and p
+      cpx<T> vj = mk<T>(T(0), T(0)), vp = vj;
+#pragma unroll
+      for (int a = 0; a < B; ++a) {
+        if (r0 + a == j) vj = cj[a];
+        if (r0 + a == p) vp = cj[a];
+      }
+      const int sj = j / B, sp = p / B;
+      cpx<T> aj, ap;
+      aj.re = __shfl(vj.re, sj, 32);
+      aj.im = __shfl(vj.im, sj, 32);
+      ap.re = __shfl(vp.re, sp, 32);
+      ap.im = __shfl(vp.im, sp, 32);
+#pragma unroll
+      for (int a = 0; a < B; ++a) {
+        const int i = r0 + a;
+        cpx<T> v = cj[a];
+        if (i == j) v = ap;
+        else if (i == p) v = aj;
+        colv[par][i] = v;
+      }
+      if (tr == 0) pivs[par] = p;
+    }
+    __syncthreads();
+    const int p = pivs[par];
+    if (tid == 0) perm[j] = p;
+    // 2. the old rows j and p
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      if (r0 + a == j)
+#pragma unroll
+        for (int b = 0; b < B; ++b) rowj[par][c0 + b] = m[a][b];
+      if (r0 + a == p)
+#pragma unroll
+        for (int b = 0; b < B; ++b) rowp[par][c0 + b] = m[a][b];
+    }
+    __syncthreads();
+    const cpx<T> piv = colv[par][j];
+    if (piv.re == T(0) && piv.im == T(0) && tid == 0) atomicExch(flag, 1);
+    const cpx<T> inv = cinv(piv);
+    // 3. Gauss-Jordan update of the own sub-block
+    cpx<T> rv[B], cv[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) rv[b] = rowp[par][c0 + b] * inv;
+#pragma unroll
+    for (int a = 0; a < B; ++a) cv[a] = colv[par][r0 + a];
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = r0 + a, jj = c0 + b;
+        if (i >= n || jj >= n) continue;
+        if (i == j) {
+          m[a][b] = jj == j ? inv : rv[b];
+        } else if (jj == j) {
+          m[a][b] = -(cv[a] * inv);
+        } else {
+          cpx<T> cur = i == p ? rowj[par][jj] : m[a][b];
+          cur.re = fma(-cv[a].re, rv[b].re, cur.re);
+          cur.re = fma(cv[a].im, rv[b].im, cur.re);
+          cur.im = fma(-cv[a].re, rv[b].im, cur.im);
+          cur.im = fma(-cv[a].im, rv[b].re, cur.im);
+          m[a][b] = cur;
+        }
+      }
+  }
+  // undo the interchanges on the columns: the column j of the eliminated
+  // block ends at place[j]
+  __syncthreads();
+  if (tid == 0) {
+    // src[pos] = eliminated column found at result position pos after the
+    // column interchanges j <-> perm[j], last first
+    for (int c = 0; c < n; ++c) src[c] = c;
+    for (int j = n - 1; j >= 0; --j) {
+      const int q = perm[j];
+      if (q != j) {
+        int t = src[j];
+        src[j] = src[q];
+        src[q] = t;
+      }
+    }
+    for (int c = 0; c < n; ++c) place[src[c]] = c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int i = r0 + a, jj = c0 + b;
+      if (i >= nP || jj >= nP) continue;
+      const int col = jj < n ? place[jj] : jj;
+      M[(size_t)i * nP + col] = (i < n && jj < n) ? m[a][b] : mk<T>(T(0), T(0));
+    }
+}
+
 template <class T>
 hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle) {
   const Geometry& g = c->g;
+  const size_t xs = (size_t)g.K * g.nP * g.nP;
+#define HDSW_FREG(B)                                                                        \
+  if (g.nP <= 32 * (B)) {                                                                   \
+    hipLaunchKernelGGL((k_factor_reg<T, B>), dim3(c->nops, 2), dim3(1024), 0, c->stream,    \
+                       (cpx<T>*)c->d_X, xs, (const cpx<T>*)c->d_coefT, c->coef_stride, c->gd, \
+                       step, middle, c->d_flag, c->nops);                                   \
+    return hipGetLastError();                                                               \
+  }
+  HDSW_FREG(2)
+  HDSW_FREG(3)
+  // complex128 sub-blocks of 4 x 4 and more exceed the registers of a
+  // 1024-thread workgroup: those blocks stay on k_factor_step below
+  if (sizeof(T) == 4) {
+    HDSW_FREG(4)
+    HDSW_FREG(5)
+  }
+#undef HDSW_FREG
   int bs = 1024;
   size_t lds = 2 * g.n * sizeof(cpx<T>) + ((g.n + 3) & ~3) * sizeof(int) +
                bs * (sizeof(T) + sizeof(int));
