@@ -603,7 +603,8 @@ struct TileGeo {
 };
 __device__ inline int face_of(const GeoDev& g, int i) {
   int f = 0;
-  while (f < 2 * g.dim - 1 && i >= g.side_off[f + 1]) ++f;
+#pragma unroll
+  for (int j = 1; j < 6; ++j) f = (j < 2 * g.dim && i >= g.side_off[j]) ? j : f;
   return f;
 }
 template <class T>
@@ -615,9 +616,10 @@ __global__ void k_extract_tiled(const cpx<T>* panel, int C, cpx<T>* Tt, int col0
     int col = (int)(idx / g.NI), i = (int)(idx - (long long)col * g.NI);
     // node of dof i: plane k, in-plane p (3D)
     int f = face_of(g, i);
-    int r = i - g.side_off[f];
-    int L = r / g.side_len[f], t = r - L * g.side_len[f];
-    int axis = f >> 1, na = g.na[axis];
+    int r = i - pick(g.side_off, f);
+    const int len = pick(g.side_len, f);
+    int L = r / len, t = r - L * len;
+    int axis = f >> 1, na = pick(g.na, axis);
     int layer = (f & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
     int x, y, z;
     if (axis == 0) { x = layer; z = t / g.ne[1]; y = t - z * g.ne[1]; }
@@ -626,8 +628,8 @@ __global__ void k_extract_tiled(const cpx<T>* panel, int C, cpx<T>* Tt, int col0
     cpx<T> v = panel[((long long)z * C + col) * g.n + (long long)y * g.ne[0] + x];
     int j = col0 + col;
     int fj = face_of(g, j);
-    int prow = tg.roff[f] + r;
-    int pcol = tg.koff[fj] + (j - g.side_off[fj]);
+    int prow = pick(tg.roff, f) + r;
+    int pcol = pick(tg.koff, fj) + (j - pick(g.side_off, fj));
     long long tile = (long long)(prow >> 6) * tg.nkt + pcol / tg.tk;
     Tt[tile * 64 * tg.tk + (long long)(pcol % tg.tk) * 64 + (prow & 63)] = v;
   }

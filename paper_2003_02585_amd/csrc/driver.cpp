@@ -429,7 +429,9 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
     const size_t nx = g.ne[0], ny = g.ne[1], nz = g.ne[2];
     c->coef_stride = nz * ny * (nx + 1) + nz * (ny + 1) * nx + (nz + 1) * ny * nx + nz * ny * nx;
   }
-  size_t xbytes = g.dim == 2 ? (size_t)c->nops * g.K * g.nP * g.nP * e
+  // 2D: one spare block after the inverses, so the block solve's whole-tile
+  // loads past the last row tile stay inside the allocation (never used)
+  size_t xbytes = g.dim == 2 ? ((size_t)c->nops * g.K + 1) * g.nP * g.nP * e
                              : (size_t)c->nops * g.K * g.n * g.n * e;
   size_t tbytes = (size_t)c->nops * g.NI * g.NI * e;
   if (g.dim == 3) {
@@ -682,10 +684,10 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   if (C > c->Cmax) {
-    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_accg, c->d_y, c->d_out, c->d_gpart,
+    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_y, c->d_out, c->d_gpart,
                     c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
     for (void* p : ptrs) dev_free(c, p);
-    c->d_panel = c->d_slots = c->d_g = c->d_accg = c->d_y = c->d_out = c->d_gpart = nullptr;
+    c->d_panel = c->d_slots = c->d_g = c->d_y = c->d_out = c->d_gpart = nullptr;
     c->gpart_bytes = 0;
     c->d_xg = c->d_rg = c->d_bg = nullptr;
     c->d_part = c->d_norm = nullptr;
@@ -701,11 +703,10 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     size_t iface = (size_t)g.nsub * C * g.NI * e;
     WALLOC(c->d_panel, (size_t)g.nsub * (g.K + 1) * C * g.n * e);
     WALLOC(c->d_slots, iface * c->sch.nsweeps);
-    WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) *
-                       (g.dim == 3 ? (size_t)c->t_nkt * c->t_tk : (size_t)g.NI) * e);
-    WALLOC(c->d_accg, iface);
     WALLOC(c->d_y, iface);
     if (g.dim == 3) {
+      // the step GEMM's B operand: trace sources in the padded k space of T
+      WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) * (size_t)c->t_nkt * c->t_tk * e);
       WALLOC(c->d_out, iface);
       // split-sum partials of the plane solves: up to 4 parts of every
       // operator group's columns
@@ -763,7 +764,6 @@ static hdsw_status ddm_impl(hdsw_ctx* c, const c128* r, c128* out, int C, int ac
   HCHK(launch_extract_iface<T>(c, g.nsub, C, c->d_y, (long long)C * g.NI, g.NI));
   size_t iface = (size_t)g.nsub * C * g.NI * e;
   HCHK(launch_zero(c, c->d_slots, iface * s.nsweeps));
-  HCHK(launch_zero(c, c->d_accg, iface));
   for (int L = 0; L < s.nsweeps; ++L) {
     for (int st = 0; st < s.nsteps; ++st) {
       int off = s.step_off[L * s.nsteps + st], cnt = s.step_cnt[L * s.nsteps + st];
@@ -805,7 +805,7 @@ static size_t max_cols(hdsw_ctx* c) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   size_t per_col = (size_t)g.nsub * (g.K + 1) * g.n * e +
-                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 3 : 2)) +
+                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 3 : 1)) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
   if (g.dim == 3) per_col += (size_t)4 * c->nops * c->grp_maxcnt * g.n * e;

@@ -19,6 +19,18 @@ struct alignas(2 * sizeof(T)) cpx {
   T re, im;
 };
 
+// a[i] for a small array held in a kernel argument and a per-lane index i:
+// a select over constant indices keeps the elements in scalar registers,
+// where a[i] would become a dependent vector load from the argument
+// segment in every lane.
+template <int N>
+__device__ __forceinline__ int pick(const int (&a)[N], int i) {
+  int v = __builtin_amdgcn_readfirstlane(a[0]);
+#pragma unroll
+  for (int j = 1; j < N; ++j) v = i == j ? __builtin_amdgcn_readfirstlane(a[j]) : v;
+  return v;
+}
+
 template <class T>
 __host__ __device__ inline cpx<T> mk(T r, T i) {
   cpx<T> z;
@@ -210,8 +222,7 @@ struct hdsw_ctx {
   int Cmax = 0;
   void* d_panel = nullptr;          // [nsub][K+1][C][n] (line K: scratch)
   void* d_slots = nullptr;          // [nsweeps][nsub][C][NI]
-  void* d_g = nullptr;              // [nsub][Cp/8][NI][8] sources of a step
-  void* d_accg = nullptr;           // [nsub][C][NI] accumulated sources
+  void* d_g = nullptr;              // 3D: [nsub][Cp][padded k] sources of a step
   void* d_y = nullptr;              // [nsub][C][NI] source-driven outputs
   void* d_out = nullptr;            // [nsub][C][NI] step outputs (3D)
   void* d_gpart = nullptr;          // split-sum partial products (3D plane solves)

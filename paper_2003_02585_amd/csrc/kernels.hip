@@ -63,27 +63,39 @@ __device__ inline int face_t(const GeoDev& g, int axis, const Loc& l) {
   if (axis == 1) return l.z * g.ne[0] + l.x;
   return l.y * g.ne[0] + l.x;
 }
-// interface dof of a local node on the faces normal to `axis`, -1 if none
-// (layer 0: the subdomain's boundary layer, layer 1: the next one out)
-__device__ inline int iface_dof(const GeoDev& g, int axis, const Loc& l) {
-  const int W = g.W, na = g.na[axis], pa = l.at(axis);
-  int s = -1, L = 0;
+// face f, layer L and tangential index t of a local node on the faces
+// normal to `axis` (layer 0: the subdomain's boundary layer, layer 1: the
+// next one out); false if the node is on neither layer
+__device__ inline bool iface_parts(const GeoDev& g, int axis, const Loc& l, int& f, int& L,
+                                   int& t) {
+  const int W = g.W, na = pick(g.na, axis), pa = l.at(axis);
+  int s = -1;
+  L = 0;
   if (pa == W) { s = 0; L = 0; }
   else if (pa == W - 1) { s = 0; L = 1; }
   else if (pa == W + na - 1) { s = 1; L = 0; }
   else if (pa == W + na) { s = 1; L = 1; }
-  if (s < 0) return -1;
-  const int f = 2 * axis + s;
-  return g.side_off[f] + L * g.side_len[f] + face_t(g, axis, l);
+  if (s < 0) return false;
+  f = 2 * axis + s;
+  t = face_t(g, axis, l);
+  return true;
+}
+// interface dof of a local node on the faces normal to `axis`, -1 if none
+__device__ inline int iface_dof(const GeoDev& g, int axis, const Loc& l) {
+  int f, L, t;
+  if (!iface_parts(g, axis, l, f, L, t)) return -1;
+  return pick(g.side_off, f) + L * pick(g.side_len, f) + t;
 }
 // local node of interface dof i
 __device__ inline Loc dof_node(const GeoDev& g, int i) {
   int f = 0;
-  while (f < 2 * g.dim - 1 && i >= g.side_off[f + 1]) ++f;
-  const int r = i - g.side_off[f];
-  const int L = r / g.side_len[f];
-  const int t = r - L * g.side_len[f];
-  const int axis = f >> 1, na = g.na[axis];
+#pragma unroll
+  for (int j = 1; j < 6; ++j) f = (j < 2 * g.dim && i >= g.side_off[j]) ? j : f;
+  const int len = pick(g.side_len, f);
+  const int r = i - pick(g.side_off, f);
+  const int L = r / len;
+  const int t = r - L * len;
+  const int axis = f >> 1, na = pick(g.na, axis);
   const int layer =
       (f & 1) == 0 ? (L == 0 ? g.W : g.W - 1) : (L == 0 ? g.W + na - 1 : g.W + na);
   Loc l;
@@ -252,14 +264,24 @@ hipError_t launch_cast_coef(hdsw_ctx* c) {
 // (factorization kernels: mfma.hip)
 
 // ------------------------------------------------------------ panels
+// Sources received over the sweeps of one DDM application: for every face,
+// the sweeps whose slot can hold a trace across it (bit L of mask[face]).
+struct TraceSum {
+  int nsweeps;
+  int mask[6];
+};
+
 // mode 0: owned part of a global FP64 vector, cast to the working precision
-// mode 1: mode 0 plus the accumulated interface sources (scatter P_I^T)
+// mode 1: mode 0 plus the interface sources received in every sweep
+//         (scatter P_I^T of sum_L g_L, g_L = [S_r, chi_r] of the pairs in
+//         slot L), summed in sweep order
 // mode 2: unit vectors of interface dofs unit_col0 .. unit_col0 + C - 1
 // batch entry b is subdomain ids[b] (modes 0, 1) or operator ids[b] (mode 2)
 template <class T>
 __global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch,
-                             int C, const c128* rg, const cpx<T>* accg, GeoDev g,
-                             long long glob, int col0) {
+                             int C, const c128* rg, const cpx<T>* __restrict__ slots,
+                             const cpx<T>* __restrict__ cface, const int* __restrict__ op_of,
+                             TraceSum ts, GeoDev g, long long glob, int col0) {
   const int n = g.n, K = g.K;
   long long per = (long long)K * C * n;
   long long tot = per * nbatch;
@@ -282,10 +304,23 @@ __global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch
       long long G = owned_global(g, sub_coords(g, s), loc);
       if (G >= 0) v = ccast<T>(rg[(long long)col * glob + G]);
       if (mode == 1) {
-        const cpx<T>* a = accg + ((long long)s * C + col) * g.NI;
+        const size_t slot_stride = (size_t)g.nsub * C * g.NI;
+        const cpx<T>* recv = slots + ((size_t)s * C + col) * g.NI;
         for (int ax = 0; ax < g.dim; ++ax) {
-          int d = iface_dof(g, ax, loc);
-          if (d >= 0) v = v + a[d];
+          int f, L, t;
+          if (!iface_parts(g, ax, loc, f, L, t)) continue;
+          // g[layer 1] = c pair[layer 0], g[layer 0] = -c pair[layer 1]
+          const int len = pick(g.side_len, f), so = pick(g.side_off, f);
+          const int partner = so + (1 - L) * len + t, mask = pick(ts.mask, f);
+          const cpx<T> cf = cface[(size_t)op_of[s] * (g.NI / 2) + so / 2 + t];
+          cpx<T> a = mk<T>(T(0), T(0));
+          for (int sw = 0; sw < ts.nsweeps; ++sw) {
+            if (!((mask >> sw) & 1)) continue;
+            cpx<T> gv = cf * recv[sw * slot_stride + partner];
+            if (L == 0) gv = -gv;
+            a = a + gv;
+          }
+          v = v + a;
         }
       }
     }
@@ -298,9 +333,15 @@ hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids
                              int C, const c128* rglob, int unit_col0) {
   long long tot = (long long)c->g.K * C * c->g.n * nbatch;
   int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  TraceSum ts{};
+  ts.nsweeps = c->sch.nsweeps;
+  for (int L = 0; L < c->sch.nsweeps; ++L)
+    for (int f = 0; f < 6; ++f)
+      if (c->sch.in_active[L * 6 + f]) ts.mask[f] |= (int)(1u << L);   // nsweeps <= 32
   hipLaunchKernelGGL(k_fill_panel<T>, dim3(blocks), dim3(256), 0, c->stream,
                      (cpx<T>*)c->d_panel, mode, d_ids, nbatch, C, rglob,
-                     (const cpx<T>*)c->d_accg, c->gd, c->g.glob_nodes, unit_col0);
+                     (const cpx<T>*)c->d_slots, (const cpx<T>*)c->d_cface, c->d_op_of_sub, ts,
+                     c->gd, c->g.glob_nodes, unit_col0);
   return hipGetLastError();
 }
 

@@ -42,18 +42,36 @@ struct WaveTiles {
   cpx<T> x[KSB][MAXT];
 };
 
+// Loads under a branch make the compiler wait for every load in flight
+// before the first use; unconditional loads let it count them.  The latter
+// is faster for complex128 blocks and slower for complex64 ones (measured
+// on the 1024^2 workload: 0.91 vs 1.00 ms and 0.73 vs 0.64 ms per launch),
+// so the form follows the precision.  Unconditionally, a slice past k1
+// re-reads slice k1 - 1 and a tile past nt reads past the block's last row
+// (at most MAXT - nt tiles, kept in bounds by the spare block after the
+// inverses); neither value is used.
+template <class T>
+struct CountedLoads { static constexpr bool v = sizeof(T) == 8; };
+
 template <class T, int MAXT, int KSB>
 __device__ __forceinline__ void mv_load(WaveTiles<T, MAXT, KSB>& w, const cpx<T>* __restrict__ Xb,
                                         int nP, int t0, int nt, int kb0, int k1, int kk, int rr) {
   const cpx<T>* base = Xb + (size_t)(t0 * 16 + rr);
 #pragma unroll
   for (int q = 0; q < KSB; ++q) {
-    const int ks = kb0 + q;
-    if (ks < k1) {
+    if constexpr (CountedLoads<T>::v) {
+      const int ks = max(0, min(kb0 + q, k1 - 1));
       const cpx<T>* xc = base + (size_t)(4 * ks + kk) * nP;
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t)
-        if (t < nt) w.x[q][t] = xc[t * 16];
+      for (int t = 0; t < MAXT; ++t) w.x[q][t] = xc[t * 16];
+    } else {
+      const int ks = kb0 + q;
+      if (ks < k1) {
+        const cpx<T>* xc = base + (size_t)(4 * ks + kk) * nP;
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t)
+          if (t < nt) w.x[q][t] = xc[t * 16];
+      }
     }
   }
 }
@@ -205,7 +223,9 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (idx < 8 * n && c < nc) {
+      const bool ok = idx < 8 * n && c < nc;
+      if (CountedLoads<T>::v || ok) {
+        if (!ok) c = r = 0;        // unused value: keeps the load unconditional
         fpre[q] = pb[((size_t)kn * C + c0 + c) * n + r];
         apre[q] = ay[(size_t)face * n + r];
       }
@@ -282,7 +302,11 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (idx < 8 * n && c < nc) apre[q] = ay[(size_t)face * n + r];
+      const bool ok = idx < 8 * n && c < nc;
+      if (CountedLoads<T>::v || ok) {
+        if (!ok) r = 0;
+        apre[q] = ay[(size_t)face * n + r];
+      }
     }
     block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)mid * nP * nP,
                                     nsteps > 0 ? Xo + (size_t)k * nP * nP : nullptr, nP, vc,
@@ -311,7 +335,9 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (idx < 8 * n && c < nc) {
+      const bool ok = idx < 8 * n && c < nc;
+      if (CountedLoads<T>::v || ok) {
+        if (!ok) c = r = 0;
         wpre[q] = pb[((size_t)k * C + c0 + c) * n + r];
         apre[q] = ay[(size_t)face * n + r];
       }
@@ -791,51 +817,21 @@ struct FaceSet {
   int start[6];          // first row (or sum index) of the face
   int lq[6];             // destination sweep per face (outputs only)
 };
+// Subdomains of one launch of a step and their operators, as a kernel
+// argument: a workgroup reads its own entry with a scalar load, so every
+// address of the step is known at the start instead of after a chain of
+// dependent memory loads.
+constexpr int kStepListMax = 64;
+struct StepList {
+  int n;
+  int sub[kStepListMax], op[kStepListMax];
+};
 __device__ inline int fs_find(const FaceSet& fs, int idx) {
+  // the last active face that starts at or before idx (starts increase)
   int q = 0;
-  while (q + 1 < fs.n && idx >= fs.start[q + 1]) ++q;
+#pragma unroll
+  for (int j = 1; j < 6; ++j) q = (j < fs.n && idx >= fs.start[j]) ? j : q;
   return q;
-}
-
-// Trace -> source for every subdomain of the step, once:
-//   g[layer 1] = c pair[layer 0],  g[layer 0] = -c pair[layer 1],
-// written in the GEMM's operand layout gbuf[s][ct][k][8] (k over the active
-// input faces, 8-column tiles, zero-padded columns) and added to the
-// sources accumulated for the final owned-node solve.
-template <class T>
-__global__ void k_trace_src(const cpx<T>* __restrict__ cface, const cpx<T>* __restrict__ slots,
-                            cpx<T>* gbuf, cpx<T>* accg, const int* __restrict__ op_of,
-                            const int* __restrict__ subs, int cnt, int L, int C, int Cp,
-                            FaceSet fin, int nin, GeoDev g) {
-  const int NI = g.NI;
-  const size_t slot_stride = (size_t)g.nsub * C * NI;
-  long long tot = (long long)cnt * Cp * nin;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int bi = (int)(idx / ((long long)Cp * nin));
-    int r = (int)(idx - (long long)bi * Cp * nin);
-    int ct = r / (nin * 8);
-    int r2 = r - ct * nin * 8;
-    int k = r2 >> 3, cl = r2 & 7;
-    int col = ct * 8 + cl;
-    int s = subs[bi];
-    cpx<T> gv = mk<T>(T(0), T(0));
-    if (col < C) {
-      int q = fs_find(fin, k);
-      int f = fin.face[q];
-      int len = g.side_len[f];
-      int rq = k - fin.start[q];
-      int lay = rq / len, t = rq - lay * len;
-      int d = g.side_off[f] + rq;
-      int partner = g.side_off[f] + (1 - lay) * len + t;
-      const cpx<T>* sl = slots + (size_t)L * slot_stride + ((size_t)s * C + col) * NI;
-      gv = cface[(size_t)op_of[s] * (NI / 2) + g.side_off[f] / 2 + t] * sl[partner];
-      if (lay == 0) gv = -gv;
-      size_t o = ((size_t)s * C + col) * NI + d;
-      accg[o] = accg[o] + gv;
-    }
-    gbuf[(size_t)s * Cp * NI + ((size_t)ct * nin + k) * 8 + cl] = gv;
-  }
 }
 
 // Epilogue of the sweep step for one output element: where its value goes.
@@ -849,12 +845,12 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
   StepOut o{-1, -1, -1};
   const int NI = g.NI;
   int q = fs_find(fout, orow);
-  int f = fout.face[q];
-  int lq = fout.lq[q];
-  int len = g.side_len[f];
-  int rq = orow - fout.start[q];
+  int f = pick(fout.face, q);
+  int lq = pick(fout.lq, q);
+  int len = pick(g.side_len, f), so = pick(g.side_off, f);
+  int rq = orow - pick(fout.start, q);
   int lay = rq / len, t = rq - lay * len;
-  int d = g.side_off[f] + rq;
+  int d = so + rq;
   int c0 = s % g.P[0], c1 = (s / g.P[0]) % g.P[1], c2 = s / (g.P[0] * g.P[1]);
   const int axis = f >> 1, step = (f & 1) ? 1 : -1;
   if (axis == 0) c0 += step;
@@ -862,17 +858,25 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
   else c2 += step;
   if (c0 < 0 || c0 >= g.P[0] || c1 < 0 || c1 >= g.P[1] || c2 < 0 || c2 >= g.P[2]) return o;
   int recv = c0 + g.P[0] * (c1 + g.P[1] * c2);
-  int fo = f ^ 1;
+  const int sofo = pick(g.side_off, f ^ 1);
   size_t rb = (size_t)lq * slot_stride + ((size_t)recv * C + col) * NI;
   if (add_y) o.yo = (long long)(((size_t)s * C + col) * NI + d);
   if (lay == 1) {
-    o.dst = (long long)(rb + g.side_off[fo] + t);
+    o.dst = (long long)(rb + sofo + t);
   } else {
-    o.dst = (long long)(rb + g.side_off[fo] + len + t);
-    o.ino = (long long)((size_t)L * slot_stride + ((size_t)s * C + col) * NI + g.side_off[f] + t);
+    o.dst = (long long)(rb + sofo + len + t);
+    o.ino = (long long)((size_t)L * slot_stride + ((size_t)s * C + col) * NI + so + t);
   }
   return o;
 }
+
+// Longest face chunk of the sum staged in LDS at once (a multiple of 4):
+// 2 tiles x lcap rows of kSweepRS operand pairs = 136 KB.  Rows hold 16
+// pairs and one of padding, so that the staging stores (one row per lane)
+// and the operand reads (four rows per wave) are free of bank conflicts.
+template <class T>
+__host__ __device__ constexpr int sweep_lcap() { return sizeof(T) == 4 ? 512 : 256; }
+constexpr int kSweepRS = 17;
 
 // The sum runs face by face over the active input faces.  For each face the
 // B operand is staged in LDS already split for the two real MFMAs of the
@@ -883,34 +887,92 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
 // so its operand is walked by pointer increments.
 template <class T, int KB, int RW>
 __global__ __launch_bounds__(512) void k_sweep_step(
-    const cpx<T>* __restrict__ Tm, const cpx<T>* __restrict__ gbuf, cpx<T>* slots,
-    const cpx<T>* __restrict__ ybuf, const int* __restrict__ op_of,
-    const int* __restrict__ subs, int L, int C, int Cp, FaceSet fin, int nin, FaceSet fout,
+    const cpx<T>* __restrict__ Tm, const cpx<T>* __restrict__ cface, cpx<T>* slots,
+    const cpx<T>* __restrict__ ybuf, StepList sl, int L, int C, FaceSet fin, FaceSet fout,
     int nout, int add_y, int LMAX, int nsub_chunks, GeoDev g) {
   typedef typename MF<T>::v4 v4;
   // RW 16-row tiles per workgroup; the 8 waves split the sum in KH parts
   constexpr int KH = 8 / RW, RWS = 16 * RW, NQ = (RWS * 16 + 511) / 512;
   extern __shared__ unsigned char smem_raw[];
-  cpx<T>* bp = reinterpret_cast<cpx<T>*>(smem_raw);        // [2 tiles][LMAX][16] pairs
+  cpx<T>* bp = reinterpret_cast<cpx<T>*>(smem_raw);        // [2 tiles][LMAX][kSweepRS] pairs
   const int NI = g.NI;
   // XCD-aware mapping: workgroups are dispatched round-robin over the 8
   // XCDs, so ids with the same id % 8 share an L2.  All subdomains of one
   // row tile get the same XCD, so its slice of T is fetched into that L2.
   const int nrt = (nout + RWS - 1) / RWS;
-  const int cnt = gridDim.x / (8 * ((nrt + 7) / 8));
+  const int cnt = sl.n;
   const int xcd = blockIdx.x & 7, q8 = blockIdx.x >> 3;
   const int rtile = xcd + 8 * (q8 / cnt);
   if (rtile >= nrt) return;
-  const int s = subs[q8 % cnt];
+  const int s = sl.sub[q8 % cnt], op = sl.op[q8 % cnt];
   const int cg = blockIdx.y;                               // 16-column group
   const int c0 = cg * 16;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int rw = wave % RW, kh = wave / RW;                // row tile, part of the sum
-  const int op = op_of[s];
   const cpx<T>* Top = Tm + (size_t)op * NI * NI;
   const size_t slot_stride = (size_t)g.nsub * C * NI;
-  const cpx<T>* gsrc = gbuf + (size_t)s * Cp * NI;
+  const cpx<T>* recv = slots + (size_t)L * slot_stride + (size_t)s * C * NI;
+  const cpx<T>* cf_op = cface + (size_t)op * (NI / 2);
   const int jc = lane & 15, kk = lane >> 4, rr = lane & 15;
+  // The B operand, g = [S_r, chi_r] v~ of the pairs received in slot L
+  // (g[layer 1] = c pair[layer 0], g[layer 0] = -c pair[layer 1], c the
+  // receiver's face coefficient), is formed while it is staged in LDS, one
+  // face chunk at a time.  Each thread holds its share of a chunk (2 tiles
+  // x 4 nks x 8 values, at most SJ per thread) in registers: the loads of
+  // the next chunk are issued before the current chunk's sum.
+  // Wave w stages column w of both 8-column tiles, lane l the sum indices
+  // k = l + 64 i: the loads of a wave read 64 consecutive sources of one
+  // column.  SK blocks of 64 indices cover the longest chunk.
+  constexpr int SK = sweep_lcap<T>() / 64;
+  cpx<T> sv[2 * SK], cv[SK];
+  const int nqc = fin.n * nsub_chunks;
+  auto chunk_len = [&](int q) {                // sum length of chunk q (0: none)
+    const int qf = q / nsub_chunks, sc = q - qf * nsub_chunks;
+    return max(0, min(LMAX, 2 * pick(g.side_len, pick(fin.face, qf)) - sc * LMAX));
+  };
+  const int scol0 = 2 * cg * 8 + wave, scol1 = scol0 + 8;   // tile 0 / tile 1 column
+  const bool ok0 = scol0 < C, ok1 = scol1 < C;
+  const cpx<T>* rcol0 = recv + (size_t)(ok0 ? scol0 : 0) * NI;
+  const cpx<T>* rcol1 = recv + (size_t)(ok1 ? scol1 : 0) * NI;
+  cpx<T>* lds_st = bp + (size_t)lane * kSweepRS + wave;
+  auto stage_load = [&](int q) {
+    const int qf = q / nsub_chunks, sc = q - qf * nsub_chunks;
+    const int f = pick(fin.face, qf);
+    const int len = pick(g.side_len, f), so = pick(g.side_off, f);
+    const int kn = chunk_len(q), kb = sc * LMAX;
+#pragma unroll
+    for (int i = 0; i < SK; ++i) {
+      // unconditional loads (indices past the chunk re-read its first
+      // source and are masked at the store), so they stay in flight together
+      const int k = lane + 64 * i;
+      const int kf = kb + (k < kn ? k : 0);    // index within the face's 2 len sources
+      const bool lay1 = kf >= len;
+      const int partner = so + kf + (lay1 ? -len : len);   // the pair's other layer
+      sv[2 * i] = rcol0[partner];
+      sv[2 * i + 1] = rcol1[partner];
+      cv[i] = cf_op[so / 2 + kf - (lay1 ? len : 0)];
+    }
+  };
+  auto stage_store = [&](int q) {
+    const int qf = q / nsub_chunks, sc = q - qf * nsub_chunks;
+    const int len = pick(g.side_len, pick(fin.face, qf));
+    const int kn = chunk_len(q), k4 = (kn + 3) & ~3, kb = sc * LMAX;
+#pragma unroll
+    for (int i = 0; i < SK; ++i) {
+      const int k = lane + 64 * i;
+      if (k < k4) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          cpx<T> gv = cv[i] * sv[2 * i + t];
+          if (kb + k < len) gv = -gv;          // layer 0 receives -c pair[layer 1]
+          if (!(k < kn && (t ? ok1 : ok0))) gv = mk<T>(T(0), T(0));
+          cpx<T>* row = lds_st + ((size_t)t * LMAX + 64 * i) * kSweepRS;
+          row[0] = mk<T>(gv.re, -gv.im);
+          row[8] = mk<T>(gv.im, gv.re);
+        }
+      }
+    }
+  };
   // epilogue operands do not depend on the product: fetch them first
   StepOut eo[NQ];
   cpx<T> ey[NQ], ein[NQ], edst[NQ];
@@ -934,46 +996,41 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   int dout = -1;
   if (row < nout) {
     int q = fs_find(fout, row);
-    dout = g.side_off[fout.face[q]] + (row - fout.start[q]);
+    dout = pick(g.side_off, pick(fout.face, q)) + (row - pick(fout.start, q));
   }
+  int qc = 0;
+  while (qc < nqc && chunk_len(qc) == 0) ++qc;
+  if (qc < nqc) stage_load(qc);
   v4 aR0 = v4{T(0), T(0), T(0), T(0)}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
-  for (int qc = 0; qc < fin.n * nsub_chunks; ++qc) {
+  while (qc < nqc) {
+    int qn = qc + 1;
+    while (qn < nqc && chunk_len(qn) == 0) ++qn;
     const int qf = qc / nsub_chunks, sc = qc - qf * nsub_chunks;
-    const int f = fin.face[qf];
-    const int flen = 2 * g.side_len[f];
+    const int f = pick(fin.face, qf);
     const int kb = sc * LMAX;                  // chunk of this face's sum
-    if (kb >= flen) continue;
-    const int kn = min(LMAX, flen - kb);       // sum length of this chunk
-    const int kst = fin.start[qf] + kb;        // its offset in the staged sources
+    const int kn = chunk_len(qc);              // sum length of this chunk
     const int nks = (kn + 3) >> 2;             // 4-deep slices, last one padded
     __syncthreads();
-    for (int idx = tid; idx < 2 * (4 * nks) * 8; idx += 512) {
-      int t = idx / (4 * nks * 8), r = idx - t * 4 * nks * 8;
-      int k = r >> 3, c = r & 7;
-      cpx<T> v;
-      v.re = T(0);
-      v.im = T(0);
-      if (k < kn) v = gsrc[((size_t)(2 * cg + t) * nin + kst + k) * 8 + c];
-      cpx<T>* row16 = bp + ((size_t)t * LMAX + k) * 16;
-      row16[c] = mk<T>(v.re, -v.im);
-      row16[c + 8] = mk<T>(v.im, v.re);
-    }
+    stage_store(qc);
     __syncthreads();
+    if (qn < nqc) stage_load(qn);              // in flight during this chunk's sum
     // this wave's part of the slices
     const int hh = (nks + KH - 1) / KH;
     const int ksb = kh * hh, kse = min(nks, ksb + hh);
-    const cpx<T>* ap = Top + (size_t)(g.side_off[f] + kb + kk) * NI + (dout >= 0 ? dout : 0);
-    const size_t astep = (size_t)4 * NI;
-    const cpx<T>* b0 = bp + (size_t)kk * 16 + jc;
-    const cpx<T>* b1 = bp + (size_t)(LMAX + kk) * 16 + jc;
+    // uniform base of the chunk's T columns, 32-bit per-lane offsets
+    const cpx<T>* abase = Top + (size_t)(pick(g.side_off, f) + kb) * NI;
+    const unsigned arow = dout >= 0 ? dout : 0;
+    const cpx<T>* b0 = bp + (size_t)kk * kSweepRS + jc;
+    const cpx<T>* b1 = bp + (size_t)(LMAX + kk) * kSweepRS + jc;
     cpx<T> a0[KB], a1[KB];
+    // unconditional loads: a slice past this wave's range is never used, a
+    // sum index past the chunk meets a zero operand in LDS, and a row past
+    // nout is not written out
     auto load = [&](cpx<T>(&a)[KB], int ks0) {
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
-        int ks = ks0 + u;
-        a[u].re = T(0);
-        a[u].im = T(0);
-        if (ks < kse && 4 * ks + kk < kn && dout >= 0) a[u] = ap[(size_t)ks * astep];
+        const int ks = max(0, min(ks0 + u, kse - 1));
+        a[u] = abase[(unsigned)min(4 * ks + kk, kn - 1) * (unsigned)NI + arow];
       }
     };
     auto compute = [&](const cpx<T>(&a)[KB], int ks0) {
@@ -981,8 +1038,8 @@ __global__ __launch_bounds__(512) void k_sweep_step(
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         const int ks = min(ks0 + u, nks - 1);
-        p0[u] = b0[(size_t)ks * 64];
-        p1[u] = b1[(size_t)ks * 64];
+        p0[u] = b0[(size_t)ks * 4 * kSweepRS];
+        p1[u] = b1[(size_t)ks * 4 * kSweepRS];
       }
       if (ks0 + KB <= kse) {
 #pragma unroll
@@ -1011,6 +1068,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
       load(a0, ks0 + 2 * KB);
       if (ks0 + KB < kse) compute(a1, ks0 + KB);
     }
+    qc = qn;
   }
   __syncthreads();
   // add the KH parts in a fixed order and stage the RWS x 16 tile:
@@ -1060,7 +1118,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
 // maps select the active faces), and the routing epilogue below.
 template <class T>
 __global__ void k_trace_src_plain(const cpx<T>* __restrict__ cface,
-                                  const cpx<T>* __restrict__ slots, cpx<T>* gplain, cpx<T>* accg,
+                                  const cpx<T>* __restrict__ slots, cpx<T>* gplain,
                                   const int* __restrict__ op_of, const int* __restrict__ subs,
                                   int cnt, int L, int C, FaceSet fin, int nin, GeoDev g) {
   const int NI = g.NI;
@@ -1073,21 +1131,18 @@ __global__ void k_trace_src_plain(const cpx<T>* __restrict__ cface,
     int col = (int)(bc % C), bi = (int)(bc / C);
     int s = subs[bi];
     int q = fs_find(fin, k);
-    int f = fin.face[q];
-    int len = g.side_len[f];
-    int rq = k - fin.start[q];
+    int f = pick(fin.face, q);
+    int len = pick(g.side_len, f), so = pick(g.side_off, f);
+    int rq = k - pick(fin.start, q);
     if (rq >= 2 * len) {             // padding of the face to whole tiles
       gplain[idx] = mk<T>(T(0), T(0));
       continue;
     }
     int lay = rq / len, t = rq - lay * len;
-    int d = g.side_off[f] + rq;
-    int partner = g.side_off[f] + (1 - lay) * len + t;
+    int partner = so + (1 - lay) * len + t;
     const cpx<T>* sl = slots + (size_t)L * slot_stride + ((size_t)s * C + col) * NI;
-    cpx<T> gv = cface[(size_t)op_of[s] * (NI / 2) + g.side_off[f] / 2 + t] * sl[partner];
+    cpx<T> gv = cface[(size_t)op_of[s] * (NI / 2) + so / 2 + t] * sl[partner];
     if (lay == 0) gv = -gv;
-    size_t o = ((size_t)s * C + col) * NI + d;
-    accg[o] = accg[o] + gv;
     gplain[idx] = gv;
   }
 }
@@ -1125,12 +1180,13 @@ __global__ void k_face_coef(cpx<T>* cface, const cpx<T>* coefT, size_t cstride, 
        idx += gridDim.x * blockDim.x) {
     int op = idx / half, i = idx - op * half;
     int f = 0;
-    while (f < 2 * g.dim - 1 && i >= g.side_off[f + 1] / 2) ++f;
-    int t = i - g.side_off[f] / 2;
+#pragma unroll
+    for (int j = 1; j < 6; ++j) f = (j < 2 * g.dim && i >= g.side_off[j] / 2) ? j : f;
+    int t = i - pick(g.side_off, f) / 2;
     const cpx<T>* co = coefT + (size_t)op * cstride;
     const int axis = f >> 1;
     // half-point index across the face, between layer 0 and layer 1
-    const int q = (f & 1) ? g.W + g.na[axis] : g.W;
+    const int q = (f & 1) ? g.W + pick(g.na, axis) : g.W;
     cpx<T> v;
     if (g.dim == 2) {
       if (f < 2) v = co[(size_t)t * (g.n + 1) + q];
@@ -1184,7 +1240,6 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
     }
   }
   if (nout == 0) return hipSuccess;
-  if (fin.n == 0) { fin.n = 1; fin.face[0] = 0; fin.start[0] = 0; }
   if (g.dim == 3) {
     const int* subs = c->d_step_subs + off;
     // input faces in the padded k space of the tiled T
@@ -1200,7 +1255,7 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
       int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
       hipLaunchKernelGGL(k_trace_src_plain<T>, dim3(blocks), dim3(256), 0, c->stream,
                          (const cpx<T>*)c->d_cface, (const cpx<T>*)c->d_slots,
-                         (cpx<T>*)c->d_g, (cpx<T>*)c->d_accg, c->d_op_of_sub, subs, cnt, L, C,
+                         (cpx<T>*)c->d_g, c->d_op_of_sub, subs, cnt, L, C,
                          finp, ninp, c->gd);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -1249,38 +1304,38 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
     return hipGetLastError();
   }
   const int Cp = (C + 15) / 16 * 16;
-  {
-    long long tot = (long long)cnt * Cp * nin;
-    int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
-    if (tot > 0)
-      hipLaunchKernelGGL(k_trace_src<T>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const cpx<T>*)c->d_cface, (const cpx<T>*)c->d_slots,
-                         (cpx<T>*)c->d_g, (cpx<T>*)c->d_accg, c->d_op_of_sub,
-                         c->d_step_subs + off, cnt, L, C, Cp, fin, nin, c->gd);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  // LDS chunks of one input face (or a part of it): 2 tiles x LMAX x 16
-  // operand pairs, LMAX a multiple of 4 that keeps the chunk at <= 128 KB
+  // LDS chunks of one input face (or a part of it): 2 tiles x LMAX rows of
+  // kSweepRS operand pairs, LMAX a multiple of 4 no larger than sweep_lcap
   int flen = 0;
   for (int q = 0; q < fin.n; ++q) flen = std::max(flen, 2 * g.side_len[fin.face[q]]);
-  const int lcap = sizeof(T) == 4 ? 512 : 256;
-  const int nsub_chunks = (flen + lcap - 1) / lcap;
-  const int LMAX = ((flen + nsub_chunks - 1) / nsub_chunks + 3) / 4 * 4;
+  const int lcap = sweep_lcap<T>();
+  const int nsub_chunks = std::max(1, (flen + lcap - 1) / lcap);
+  const int LMAX = std::max(4, ((flen + nsub_chunks - 1) / nsub_chunks + 3) / 4 * 4);
   constexpr int KB = sizeof(T) == 4 ? 8 : 4;
   // two 16-row tiles per workgroup, the sum split in four (measured best of
   // one, two and four tiles at the 1024^2 workload)
   constexpr int RW = 2;
   const int nrt = (nout + 16 * RW - 1) / (16 * RW);
-  dim3 grid(8 * ((nrt + 7) / 8) * cnt, Cp / 16, 1);
   // LDS: the staged operand pairs, or the KH partial tiles of the sum
-  size_t lds = std::max<size_t>((size_t)2 * LMAX * 16, (size_t)(8 / RW) * 16 * 16 * RW) *
+  size_t lds = std::max<size_t>((size_t)2 * LMAX * kSweepRS, (size_t)(8 / RW) * 16 * 16 * RW) *
                sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_sweep_step<T, KB, RW>), grid, dim3(512), lds, c->stream,
-                     (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_g, (cpx<T>*)c->d_slots,
-                     (const cpx<T>*)c->d_y, c->d_op_of_sub, c->d_step_subs + off, L, C, Cp,
-                     fin, nin, fout, nout, L == 0 ? 1 : 0, LMAX, nsub_chunks, c->gd);
-  return hipGetLastError();
+  // the step's subdomains in launches of at most kStepListMax
+  for (int b0 = 0; b0 < cnt; b0 += kStepListMax) {
+    StepList sl{};
+    sl.n = std::min(kStepListMax, cnt - b0);
+    for (int i = 0; i < sl.n; ++i) {
+      sl.sub[i] = c->sch.step_subs[off + b0 + i];
+      sl.op[i] = c->op_of_sub[sl.sub[i]];
+    }
+    dim3 grid(8 * ((nrt + 7) / 8) * sl.n, Cp / 16, 1);
+    hipLaunchKernelGGL((k_sweep_step<T, KB, RW>), grid, dim3(512), lds, c->stream,
+                       (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_cface, (cpx<T>*)c->d_slots,
+                       (const cpx<T>*)c->d_y, sl, L, C, fin, fout, nout, L == 0 ? 1 : 0, LMAX,
+                       nsub_chunks, c->gd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 #define HDSW_INST2(T)                                                          \

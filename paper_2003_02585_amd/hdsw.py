@@ -59,6 +59,15 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(
             f"libhdsw.so not built ({path}); run __graft_entry__.build() first")
+    # The library has to bind to the HIP runtime that the caller's device
+    # pointers and streams come from.  torch ships its own libamdhip64: when
+    # torch is installed it is imported first, so the library resolves to
+    # that runtime instead of loading a second one from the system (with two
+    # runtimes in the process, torch's streams are invalid handles here).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     c_void_p, c_int = ctypes.c_void_p, ctypes.c_int
     lib.hdsw_default_options.argtypes = [ctypes.POINTER(hdsw_options)]
