@@ -98,7 +98,12 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
   {                                                                              \
     if (TILED) {                                                                 \
       const cpx<T>* tp = atile + (long long)a.a_kt[(k0) / BK] * (GM * BK) + ar;  \
-      _Pragma("unroll") for (int u = 0; u < AL; ++u) ra[u] = tp[(ak + u) * GM];  \
+      /* field by field: a complex128 struct copy goes through private */      \
+      /* memory here */                                                          \
+      _Pragma("unroll") for (int u = 0; u < AL; ++u) {                           \
+        ra[u].re = tp[(ak + u) * GM].re;                                         \
+        ra[u].im = tp[(ak + u) * GM].im;                                         \
+      }                                                                          \
     } else {                                                                     \
       _Pragma("unroll") for (int u = 0; u < AL; ++u) {                           \
         int k = (k0) + ak + u;                                                   \
@@ -116,7 +121,8 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
   }
 #define HDSW_GEMM_STORE(buf)                                                     \
   {                                                                              \
-    _Pragma("unroll") for (int u = 0; u < AL; ++u) As[buf][ak + u][ar] = ra[u];  \
+    _Pragma("unroll") for (int u = 0; u < AL; ++u)                               \
+      As[buf][ak + u][ar] = mk<T>(ra[u].re, ra[u].im);                           \
     const int g_ = bc >> 3, cc_ = bc & 7;                                        \
     _Pragma("unroll") for (int u = 0; u < BL; ++u) {                             \
       Bp[buf][bk + u][g_ * 16 + cc_] = mk<T>(rb[u].re, -rb[u].im);               \

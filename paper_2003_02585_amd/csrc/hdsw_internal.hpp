@@ -31,6 +31,16 @@ __device__ __forceinline__ int pick(const int (&a)[N], int i) {
   return v;
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// waits for every global load in flight, which would drain prefetches issued
+// before it; kernels use this one where no global data passes between
+// threads of the workgroup.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <class T>
 __host__ __device__ inline cpx<T> mk(T r, T i) {
   cpx<T> z;

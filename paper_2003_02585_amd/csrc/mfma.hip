@@ -11,6 +11,11 @@
 // are independent, which halves the dependent chain of both the
 // factorization and every solve.
 //
+// Every barrier of the solve and sweep kernels orders LDS only: no global
+// data passes between threads of a workgroup within one launch (each thread
+// reads back only the panel entries it wrote), so prefetched loads stay in
+// flight across barriers.
+//
 // Solve with the stored inverses, two launches:
 //   A: top     w_k = X_k (f_k - B_k w_{k-1})          k = 0 .. m-1
 //      bottom  v_k = X_k (f_k - B_{k+1} v_{k+1})      k = K-1 .. m+1
@@ -28,7 +33,7 @@
 namespace hdsw {
 
 // ------------------------------------------------------------ matvec
-// yb[r][c] = sum_j Xb(r, j) vb[j][c] for 8 columns c (LDS, row-major with the
+// y[r][c] = sum_j Xb(r, j) vb[j][c] for 8 columns c (LDS, row-major with the
 // 8 columns contiguous so one 4-row slice is 64 distinct banks; zero beyond
 // n).  Waves split the rows in two halves of 16-row tiles and the sum in
 // KS = NW / 2 slices; the slices are added in a fixed order, so results do
@@ -123,17 +128,16 @@ __device__ inline WaveGeo wave_geo(int nP, int wave, int lane) {
   return w;
 }
 
-// One block product yb = X_k vc.  On entry `tiles` holds the first batch of
-// X_k; on exit it holds the first batch of Xnext (if not null).  Ends with
-// the block synchronized and yb complete.
+// One block product y = X_k vc.  On entry `tiles` holds the first batch of
+// X_k; on exit it holds the first batch of Xnext (if not null).  Every wave
+// leaves its part of the sum (rows of its half, a quarter of the columns of
+// X_k) in red[kq]; ends with the block synchronized, the parts complete.
 template <class T, int MAXT, int KSB, int NW>
 __device__ __forceinline__ void block_product(WaveTiles<T, MAXT, KSB>& tiles, const WaveGeo& wg,
                                               const cpx<T>* __restrict__ Xk,
                                               const cpx<T>* __restrict__ Xnext, int nP,
-                                              const cpx<T>* vc, cpx<T>* yb, cpx<T>* red,
-                                              int lane) {
+                                              const cpx<T>* vc, cpx<T>* red, int lane) {
   typedef typename MF<T>::v4 v4;
-  constexpr int KS = NW / 2;
   v4 acc[MAXT];
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) acc[t] = v4{T(0), T(0), T(0), T(0)};
@@ -143,34 +147,26 @@ __device__ __forceinline__ void block_product(WaveTiles<T, MAXT, KSB>& tiles, co
     mv_mfma<T, MAXT, KSB>(tiles, acc, vc, kb, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
   }
   if (Xnext) mv_load<T, MAXT, KSB>(tiles, Xnext, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk, wg.rr);
-  if (wg.kq > 0) {
-    T* dst = reinterpret_cast<T*>(red + (size_t)(wg.kq - 1) * 8 * nP);
+  T* dst = reinterpret_cast<T*>(red + (size_t)wg.kq * 8 * nP);
 #pragma unroll
-    for (int t = 0; t < MAXT; ++t)
-      if (t < wg.nt)
+  for (int t = 0; t < MAXT; ++t)
+    if (t < wg.nt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          int row = 16 * (wg.t0 + t) + MF<T>::row(lane, i);
-          dst[2 * (row * 8 + wg.cc) + wg.part] = acc[t][i];
-        }
-  }
-  __syncthreads();
-  if (wg.kq == 0) {
-    T* y = reinterpret_cast<T*>(yb);
-    const T* rd = reinterpret_cast<const T*>(red);
+      for (int i = 0; i < 4; ++i) {
+        int row = 16 * (wg.t0 + t) + MF<T>::row(lane, i);
+        dst[2 * (row * 8 + wg.cc) + wg.part] = acc[t][i];
+      }
+  lds_barrier();
+}
+
+// Entry rc = row * 8 + column of the last block product: its NW / 2 parts
+// added in a fixed order, so the result does not depend on timing.
+template <class T, int NW>
+__device__ __forceinline__ cpx<T> prod_y(const cpx<T>* red, int nP, int rc) {
+  cpx<T> y = red[rc];
 #pragma unroll
-    for (int t = 0; t < MAXT; ++t)
-      if (t < wg.nt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          int row = 16 * (wg.t0 + t) + MF<T>::row(lane, i);
-          int idx = 2 * (row * 8 + wg.cc) + wg.part;
-          T sum = acc[t][i];
-          for (int q = 0; q < KS - 1; ++q) sum += rd[(size_t)q * 16 * nP + idx];
-          y[idx] = sum;
-        }
-  }
-  __syncthreads();
+  for (int q = 1; q < NW / 2; ++q) y = y + red[(size_t)q * 8 * nP + rc];
+  return y;
 }
 
 // ------------------------------------------------------------ solve A
@@ -192,15 +188,14 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cpx<T>* vb0 = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* vb1 = vb0 + 8 * nP;
-  cpx<T>* yb = vb1 + 8 * nP;
-  cpx<T>* red = yb + 8 * nP;
+  cpx<T>* red = vb1 + 8 * nP;                     // NW / 2 parts of a product
   const int op = ops[b];
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
   cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
   const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
   for (int idx = tid; idx < 16 * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
-  __syncthreads();
+  lds_barrier();
   int k = half ? K - 1 : 0;
   const int nsteps = half ? K - 1 - mid : mid;
   for (int idx = tid; idx < 8 * n; idx += NT) {
@@ -210,7 +205,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
   WaveTiles<T, MAXT, KSB> tiles;
   mv_load<T, MAXT, KSB>(tiles, Xo + (size_t)k * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk,
                         wg.rr);
-  __syncthreads();
+  lds_barrier();
   cpx<T>* vc = vb0;
   cpx<T>* vn = vb1;
   for (int s = 0; s < nsteps; ++s) {
@@ -231,14 +226,14 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
       }
     }
     block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
-                                    more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, yb, red,
+                                    more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, red,
                                     lane);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
       if (idx < 8 * n && c < nc) {
-        cpx<T> y = yb[r * 8 + c];
+        cpx<T> y = prod_y<T, NW>(red, nP, r * 8 + c);
         pb[((size_t)k * C + c0 + c) * n + r] = y;
         cpx<T> nxt = fpre[q] - apre[q] * y;
         if (more) vn[r * 8 + c] = nxt;
@@ -246,7 +241,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
           pb[((size_t)K * C + c0 + c) * n + r] = nxt;
       }
     }
-    __syncthreads();
+    lds_barrier();
     k = kn;
     cpx<T>* t = vc;
     vc = vn;
@@ -271,15 +266,14 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cpx<T>* vb0 = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* vb1 = vb0 + 8 * nP;
-  cpx<T>* yb = vb1 + 8 * nP;
-  cpx<T>* red = yb + 8 * nP;
+  cpx<T>* red = vb1 + 8 * nP;                     // NW / 2 parts of a product
   const int op = ops[b];
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
   cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
   const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
   for (int idx = tid; idx < 16 * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
-  __syncthreads();
+  lds_barrier();
   // middle line: v = (f_m - B_m w_{m-1}) - B_{m+1} v_{m+1}
   for (int idx = tid; idx < 8 * n; idx += NT) {
     int c = idx / n, r = idx - c * n;
@@ -290,7 +284,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
   WaveTiles<T, MAXT, KSB> tiles;
   mv_load<T, MAXT, KSB>(tiles, Xo + (size_t)mid * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1,
                         wg.kk, wg.rr);
-  __syncthreads();
+  lds_barrier();
   cpx<T>* vc = vb0;
   cpx<T>* vn = vb1;
   const int nsteps = half ? K - 1 - mid : mid;
@@ -310,18 +304,18 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     }
     block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)mid * nP * nP,
                                     nsteps > 0 ? Xo + (size_t)k * nP * nP : nullptr, nP, vc,
-                                    yb, red, lane);
+                                    red, lane);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
       if (idx < 8 * n && c < nc) {
-        cpx<T> x = yb[r * 8 + c];
+        cpx<T> x = prod_y<T, NW>(red, nP, r * 8 + c);
         if (half == 0) pb[((size_t)mid * C + c0 + c) * n + r] = x;
         vn[r * 8 + c] = apre[q] * x;
       }
     }
-    __syncthreads();
+    lds_barrier();
     cpx<T>* t = vc;
     vc = vn;
     vn = t;
@@ -343,19 +337,19 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
       }
     }
     block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
-                                    more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, yb, red,
+                                    more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, red,
                                     lane);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
       if (idx < 8 * n && c < nc) {
-        cpx<T> x = wpre[q] - yb[r * 8 + c];
+        cpx<T> x = wpre[q] - prod_y<T, NW>(red, nP, r * 8 + c);
         pb[((size_t)k * C + c0 + c) * n + r] = x;
         if (more) vn[r * 8 + c] = apre[q] * x;
       }
     }
-    __syncthreads();
+    lds_barrier();
     k = kn;
     cpx<T>* t = vc;
     vc = vn;
@@ -374,8 +368,11 @@ static int solve_nw(int nP) {
 }
 
 // 4-deep slices loaded per batch: as many as fit in registers without spills
-template <class T>
-struct SolveKSB { static constexpr int v = sizeof(T) == 4 ? 5 : 3; };
+// (checked in the register report of the build for every instantiation)
+template <class T, int MAXT>
+struct SolveKSB {
+  static constexpr int v = sizeof(T) == 4 ? (MAXT <= 5 ? 5 : 2) : (MAXT == 5 ? 3 : 2);
+};
 
 template <class T, int MAXT, int NW>
 static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
@@ -385,12 +382,12 @@ static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int 
   dim3 grid((C + 7) / 8, nbatch, 2);
   size_t lds = (size_t)(2 + NW / 2) * 8 * g.nP * sizeof(cpx<T>);
   size_t xstride = (size_t)g.K * g.nP * g.nP;
-  hipLaunchKernelGGL((k_solve_fwd<T, MAXT, SolveKSB<T>::v, NW, EPT>), grid, dim3(NW * 64), lds,
+  hipLaunchKernelGGL((k_solve_fwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT>), grid, dim3(NW * 64), lds,
                      c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
                      c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve_bwd<T, MAXT, SolveKSB<T>::v, NW, EPT>), grid, dim3(NW * 64), lds,
+  hipLaunchKernelGGL((k_solve_bwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT>), grid, dim3(NW * 64), lds,
                      c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
                      c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
   return hipGetLastError();
@@ -404,8 +401,7 @@ static hipError_t launch_solve_nw(hdsw_ctx* c, int nbatch, const int* d_ops, int
   if (th <= 3) return launch_solve_t<T, 3, NW>(c, nbatch, d_ops, C);
   if (th <= 5) return launch_solve_t<T, 5, NW>(c, nbatch, d_ops, C);
   if (th <= 8) return launch_solve_t<T, 8, NW>(c, nbatch, d_ops, C);
-  if (th <= 16) return launch_solve_t<T, 16, NW>(c, nbatch, d_ops, C);
-  return hipErrorInvalidValue;
+  return hipErrorInvalidValue;   // nP <= 256 (checked at setup): at most 8 tiles per half
 }
 
 template <class T>
@@ -430,6 +426,17 @@ hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) 
   if (nw == 8) return launch_solve_nw<T, 8>(c, nbatch, d_ops, C);
   if (nw == 4) return launch_solve_nw<T, 4>(c, nbatch, d_ops, C);
   return hipErrorInvalidValue;
+}
+
+// Swaps two complex entries of global memory field by field (a struct copy
+// between two entries of one array goes through a private temporary).
+template <class T>
+__device__ __forceinline__ void swap_fields(cpx<T>* x, cpx<T>* y) {
+  const T xr = x->re, xi = x->im, yr = y->re, yi = y->im;
+  x->re = yr;
+  x->im = yi;
+  y->re = xr;
+  y->im = xi;
 }
 
 // ------------------------------------------------------------ factor
@@ -486,9 +493,10 @@ __global__ __launch_bounds__(1024) void k_factor_step(cpx<T>* X, size_t xstride,
     int i = idx / nP, j = idx - i * nP;
     cpx<T> v = mk<T>(T(0), T(0));
     if (i < n && j < n) {
-      if (i == j) v = dg[i];
-      else if (j == i + 1) v = ax[j];
-      else if (i == j + 1) v = ax[i];
+      // the source is chosen as a pointer and read field by field: a struct
+      // copy under a condition would keep v in private memory
+      const cpx<T>* src = i == j ? dg + i : j == i + 1 ? ax + j : i == j + 1 ? ax + i : nullptr;
+      if (src) v = mk<T>(src->re, src->im);
       if (PA) v = v - ay[(size_t)fa * n + i] * ay[(size_t)fa * n + j] * PA[idx];
       if (PB) v = v - ay[(size_t)fb * n + i] * ay[(size_t)fb * n + j] * PB[idx];
     }
@@ -522,11 +530,7 @@ __global__ __launch_bounds__(1024) void k_factor_step(cpx<T>* X, size_t xstride,
     if (p >= n) p = j;
     if (tid == 0) perm[j] = p;
     if (p != j) {
-      for (int jj = tid; jj < n; jj += bs) {
-        cpx<T> a = M[(size_t)j * nP + jj];
-        M[(size_t)j * nP + jj] = M[(size_t)p * nP + jj];
-        M[(size_t)p * nP + jj] = a;
-      }
+      for (int jj = tid; jj < n; jj += bs) swap_fields(M + (size_t)j * nP + jj, M + (size_t)p * nP + jj);
     }
     __threadfence_block();
     __syncthreads();
@@ -561,11 +565,7 @@ __global__ __launch_bounds__(1024) void k_factor_step(cpx<T>* X, size_t xstride,
   for (int j = n - 1; j >= 0; --j) {
     int p = perm[j];
     if (p != j) {
-      for (int i = tid; i < n; i += bs) {
-        cpx<T> a = M[(size_t)i * nP + j];
-        M[(size_t)i * nP + j] = M[(size_t)i * nP + p];
-        M[(size_t)i * nP + p] = a;
-      }
+      for (int i = tid; i < n; i += bs) swap_fields(M + (size_t)i * nP + j, M + (size_t)i * nP + p);
     }
     __threadfence_block();
     __syncthreads();
@@ -779,7 +779,7 @@ hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle) {
   HDSW_FREG(3)
   // complex128 sub-blocks of 4 x 4 and more exceed the registers of a
   // 1024-thread workgroup: those blocks stay on k_factor_step below
-  if (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4) {
     HDSW_FREG(4)
     HDSW_FREG(5)
   }
@@ -973,6 +973,84 @@ __global__ __launch_bounds__(512) void k_sweep_step(
       }
     }
   };
+  // output dof of this lane's A row
+  const int row = rtile * RWS + rw * 16 + rr;
+  int dout = -1;
+  if (row < nout) {
+    int q = fs_find(fout, row);
+    dout = pick(g.side_off, pick(fout.face, q)) + (row - pick(fout.start, q));
+  }
+  const unsigned arow = dout >= 0 ? dout : 0;
+  // this wave's share of chunk q: T columns, sum length, slice range
+  struct ChunkGeo {
+    const cpx<T>* abase;                       // uniform base, 32-bit lane offsets
+    int kn, nks, ksb, kse;
+  };
+  auto cgeo = [&](int q) {
+    ChunkGeo c;
+    const int qf = q / nsub_chunks, sc = q - qf * nsub_chunks;
+    c.kn = chunk_len(q);                       // sum length of the chunk
+    c.nks = (c.kn + 3) >> 2;                   // 4-deep slices, last one padded
+    const int hh = (c.nks + KH - 1) / KH;
+    c.ksb = kh * hh;
+    c.kse = min(c.nks, c.ksb + hh);
+    c.abase = Top + (size_t)(pick(g.side_off, pick(fin.face, qf)) + sc * LMAX) * NI;
+    return c;
+  };
+  // unconditional loads: a slice past this wave's range is never used, a
+  // sum index past the chunk meets a zero operand in LDS, and a row past
+  // nout is not written out
+  auto load = [&](cpx<T>(&a)[KB], const ChunkGeo& c, int ks0) {
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int ks = max(0, min(ks0 + u, c.kse - 1));
+      a[u] = c.abase[(unsigned)min(4 * ks + kk, c.kn - 1) * (unsigned)NI + arow];
+    }
+  };
+  const cpx<T>* b0 = bp + (size_t)kk * kSweepRS + jc;
+  const cpx<T>* b1 = bp + (size_t)(LMAX + kk) * kSweepRS + jc;
+  v4 aR0 = v4{T(0), T(0), T(0), T(0)}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+  auto compute = [&](const cpx<T>(&a)[KB], const ChunkGeo& c, int ks0) {
+    cpx<T> p0[KB], p1[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int ks = min(ks0 + u, c.nks - 1);
+      p0[u] = b0[(size_t)ks * 4 * kSweepRS];
+      p1[u] = b1[(size_t)ks * 4 * kSweepRS];
+    }
+    if (ks0 + KB <= c.kse) {
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
+        aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
+        aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
+        aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        if (ks0 + u < c.kse) {
+          aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
+          aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
+          aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
+          aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
+        }
+      }
+    }
+  };
+  // The A operand (rows of T) streams through two register batches, one
+  // batch ahead across chunk boundaries: the first batch is requested
+  // before anything else, and the last prefetch of a chunk fetches the
+  // first batch of the next one.
+  cpx<T> a0[KB], a1[KB];
+  int qc = 0;
+  while (qc < nqc && chunk_len(qc) == 0) ++qc;
+  ChunkGeo cur{};
+  if (qc < nqc) {
+    cur = cgeo(qc);
+    load(a0, cur, cur.ksb);
+    stage_load(qc);
+  }
   // epilogue operands do not depend on the product: fetch them first
   StepOut eo[NQ];
   cpx<T> ey[NQ], ein[NQ], edst[NQ];
@@ -991,86 +1069,26 @@ __global__ __launch_bounds__(512) void k_sweep_step(
     if (eo[q].ino >= 0) ein[q] = slots[eo[q].ino];
     if (eo[q].dst >= 0) edst[q] = slots[eo[q].dst];
   }
-  // output dof of this lane's A row
-  const int row = rtile * RWS + rw * 16 + rr;
-  int dout = -1;
-  if (row < nout) {
-    int q = fs_find(fout, row);
-    dout = pick(g.side_off, pick(fout.face, q)) + (row - pick(fout.start, q));
-  }
-  int qc = 0;
-  while (qc < nqc && chunk_len(qc) == 0) ++qc;
-  if (qc < nqc) stage_load(qc);
-  v4 aR0 = v4{T(0), T(0), T(0), T(0)}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
   while (qc < nqc) {
     int qn = qc + 1;
     while (qn < nqc && chunk_len(qn) == 0) ++qn;
-    const int qf = qc / nsub_chunks, sc = qc - qf * nsub_chunks;
-    const int f = pick(fin.face, qf);
-    const int kb = sc * LMAX;                  // chunk of this face's sum
-    const int kn = chunk_len(qc);              // sum length of this chunk
-    const int nks = (kn + 3) >> 2;             // 4-deep slices, last one padded
-    __syncthreads();
+    const ChunkGeo nxt = qn < nqc ? cgeo(qn) : cur;
+    lds_barrier();
     stage_store(qc);
-    __syncthreads();
+    lds_barrier();
     if (qn < nqc) stage_load(qn);              // in flight during this chunk's sum
-    // this wave's part of the slices
-    const int hh = (nks + KH - 1) / KH;
-    const int ksb = kh * hh, kse = min(nks, ksb + hh);
-    // uniform base of the chunk's T columns, 32-bit per-lane offsets
-    const cpx<T>* abase = Top + (size_t)(pick(g.side_off, f) + kb) * NI;
-    const unsigned arow = dout >= 0 ? dout : 0;
-    const cpx<T>* b0 = bp + (size_t)kk * kSweepRS + jc;
-    const cpx<T>* b1 = bp + (size_t)(LMAX + kk) * kSweepRS + jc;
-    cpx<T> a0[KB], a1[KB];
-    // unconditional loads: a slice past this wave's range is never used, a
-    // sum index past the chunk meets a zero operand in LDS, and a row past
-    // nout is not written out
-    auto load = [&](cpx<T>(&a)[KB], int ks0) {
-#pragma unroll
-      for (int u = 0; u < KB; ++u) {
-        const int ks = max(0, min(ks0 + u, kse - 1));
-        a[u] = abase[(unsigned)min(4 * ks + kk, kn - 1) * (unsigned)NI + arow];
-      }
-    };
-    auto compute = [&](const cpx<T>(&a)[KB], int ks0) {
-      cpx<T> p0[KB], p1[KB];
-#pragma unroll
-      for (int u = 0; u < KB; ++u) {
-        const int ks = min(ks0 + u, nks - 1);
-        p0[u] = b0[(size_t)ks * 4 * kSweepRS];
-        p1[u] = b1[(size_t)ks * 4 * kSweepRS];
-      }
-      if (ks0 + KB <= kse) {
-#pragma unroll
-        for (int u = 0; u < KB; ++u) {
-          aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
-          aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
-          aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
-          aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < KB; ++u) {
-          if (ks0 + u < kse) {
-            aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
-            aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
-            aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
-            aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
-          }
-        }
-      }
-    };
-    load(a0, ksb);
-    for (int ks0 = ksb; ks0 < kse; ks0 += 2 * KB) {
-      load(a1, ks0 + KB);
-      compute(a0, ks0);
-      load(a0, ks0 + 2 * KB);
-      if (ks0 + KB < kse) compute(a1, ks0 + KB);
+    if (cur.ksb >= cur.kse) load(a0, nxt, nxt.ksb);   // no slices here: move on
+    for (int ks0 = cur.ksb; ks0 < cur.kse; ks0 += 2 * KB) {
+      load(a1, cur, ks0 + KB);
+      compute(a0, cur, ks0);
+      if (ks0 + 2 * KB < cur.kse) load(a0, cur, ks0 + 2 * KB);
+      else load(a0, nxt, nxt.ksb);
+      if (ks0 + KB < cur.kse) compute(a1, cur, ks0 + KB);
     }
     qc = qn;
+    cur = nxt;
   }
-  __syncthreads();
+  lds_barrier();
   // add the KH parts in a fixed order and stage the RWS x 16 tile:
   // part p of the sum at st + p * (2 * 16 * RWS) floats, p = 0 the final tile
   T* st = reinterpret_cast<T*>(bp);
@@ -1084,7 +1102,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
       pp[2 * ((cc + 8) * RWS + r) + part] = aR1[i] + aI1[i];
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (kh == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1100,7 +1118,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
       st[i1] = v1;
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     if (eo[q].dst < 0) continue;
