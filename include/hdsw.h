@@ -157,9 +157,11 @@ hdsw_status hdsw_residual(hdsw_ctx* ctx, const hdsw_c128* b_dev,
 hdsw_status hdsw_query(const hdsw_ctx* ctx, size_t* factor_bytes,
                        int* n_distinct_ops, size_t* workspace_bytes);
 
-/* Kernel timing: when enabled, HIP events bracket every launch of kernel
- * class `which` (0 = batched block solve, 1 = sweep-step interface GEMM,
- * 2 = block factorization, 3 = FP64 residual) on the context's stream.
+/* Kernel timing: HIP events bracket every launch of the enabled kernel
+ * classes (0 = batched block solve, 1 = sweep step, 2 = block
+ * factorization, 3 = FP64 residual) on the context's stream.  `enable` is a
+ * bit mask of classes (bit k enables class k, 0 disables timing); events
+ * add a few microseconds between launches, so time only what is needed.
  * hdsw_timing_get returns the accumulated milliseconds, launch count and
  * the algorithmic flops and bytes of those launches, then resets them. */
 hdsw_status hdsw_timing_enable(hdsw_ctx* ctx, int enable);

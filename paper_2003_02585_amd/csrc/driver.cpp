@@ -205,7 +205,7 @@ struct TimedScope {
   double flops, bytes;
   int slot = -1;
   TimedScope(hdsw_ctx* c_, int cls_, double f, double b) : c(c_), cls(cls_), flops(f), bytes(b) {
-    if (!c->tm.on) return;
+    if (!((c->tm.mask >> cls) & 1)) return;
     EvPool& p = pools()[c];
     if (p.ev.empty()) {
       p.ev.resize(2 * 8192, nullptr);

@@ -157,7 +157,7 @@ struct DevBuf {
 };
 
 struct Timing {
-  bool on = false;
+  int mask = 0;                     // bit k: time kernel class k
   double ms[4] = {0, 0, 0, 0};
   long long launches[4] = {0, 0, 0, 0};
   double flops[4] = {0, 0, 0, 0};

@@ -208,7 +208,10 @@ def hdsw_query(ctx):
 
 
 def hdsw_timing_enable(ctx, enable=True):
-    _check(_lib.hdsw_timing_enable(ctx, int(bool(enable))), "hdsw_timing_enable")
+    """enable: True (every kernel class), False (none) or a bit mask of
+    classes (bit k = class k of hdsw_timing_get)."""
+    mask = (15 if enable else 0) if isinstance(enable, bool) else int(enable)
+    _check(_lib.hdsw_timing_enable(ctx, mask), "hdsw_timing_enable")
 
 
 def hdsw_timing_get(ctx, which):
