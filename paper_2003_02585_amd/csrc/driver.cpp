@@ -684,10 +684,10 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   if (C > c->Cmax) {
-    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_y, c->d_out, c->d_gpart,
+    void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_srcsum, c->d_y, c->d_out, c->d_gpart,
                     c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
     for (void* p : ptrs) dev_free(c, p);
-    c->d_panel = c->d_slots = c->d_g = c->d_y = c->d_out = c->d_gpart = nullptr;
+    c->d_panel = c->d_slots = c->d_g = c->d_srcsum = c->d_y = c->d_out = c->d_gpart = nullptr;
     c->gpart_bytes = 0;
     c->d_xg = c->d_rg = c->d_bg = nullptr;
     c->d_part = c->d_norm = nullptr;
@@ -703,6 +703,7 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     size_t iface = (size_t)g.nsub * C * g.NI * e;
     WALLOC(c->d_panel, (size_t)g.nsub * (g.K + 1) * C * g.n * e);
     WALLOC(c->d_slots, iface * c->sch.nsweeps);
+    WALLOC(c->d_srcsum, iface);
     WALLOC(c->d_y, iface);
     if (g.dim == 3) {
       // the step GEMM's B operand: trace sources in the padded k space of T
@@ -805,7 +806,7 @@ static size_t max_cols(hdsw_ctx* c) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   size_t per_col = (size_t)g.nsub * (g.K + 1) * g.n * e +
-                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 3 : 1)) +
+                   (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 4 : 2)) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
   if (g.dim == 3) per_col += (size_t)4 * c->nops * c->grp_maxcnt * g.n * e;

@@ -233,6 +233,7 @@ struct hdsw_ctx {
   void* d_panel = nullptr;          // [nsub][K+1][C][n] (line K: scratch)
   void* d_slots = nullptr;          // [nsweeps][nsub][C][NI]
   void* d_g = nullptr;              // 3D: [nsub][Cp][padded k] sources of a step
+  void* d_srcsum = nullptr;         // [nsub][C][NI] received sources, summed over sweeps
   void* d_y = nullptr;              // [nsub][C][NI] source-driven outputs
   void* d_out = nullptr;            // [nsub][C][NI] step outputs (3D)
   void* d_gpart = nullptr;          // split-sum partial products (3D plane solves)

@@ -277,22 +277,55 @@ struct TraceSum {
 //         slot L), summed in sweep order
 // mode 2: unit vectors of interface dofs unit_col0 .. unit_col0 + C - 1
 // batch entry b is subdomain ids[b] (modes 0, 1) or operator ids[b] (mode 2)
+// Sources received over the sweeps of one DDM application, per interface
+// dof: srcsum[s][c][d] = sum over the sweeps L whose slot can hold a trace
+// across the face of d of g_L[d], g = [S_r, chi_r] v~ of the pairs in slot L
+// (g[layer 1] = c pair[layer 0], g[layer 0] = -c pair[layer 1]), summed in
+// sweep order.
 template <class T>
-__global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch,
-                             int C, const c128* rg, const cpx<T>* __restrict__ slots,
+__global__ void k_source_sum(cpx<T>* srcsum, const cpx<T>* __restrict__ slots,
                              const cpx<T>* __restrict__ cface, const int* __restrict__ op_of,
-                             TraceSum ts, GeoDev g, long long glob, int col0) {
-  const int n = g.n, K = g.K;
-  long long per = (long long)K * C * n;
-  long long tot = per * nbatch;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int b = (int)(idx / per);
-    long long r = idx - b * per;
-    cpx<T>* dst = panel + (long long)b * (K + 1) * C * n + r;
-    int k = (int)(r / ((long long)C * n));
-    int rem = (int)(r - (long long)k * C * n);
-    int col = rem / n, p = rem - col * n;
+                             int C, TraceSum ts, GeoDev g) {
+  const int NI = g.NI;
+  const unsigned per = (unsigned)C * NI;
+  const int s = blockIdx.y;
+  const size_t slot_stride = (size_t)g.nsub * C * NI;
+  for (unsigned r = blockIdx.x * blockDim.x + threadIdx.x; r < per; r += gridDim.x * blockDim.x) {
+    const int col = (int)(r / (unsigned)NI), d = (int)(r - (unsigned)col * NI);
+    int f = 0;
+#pragma unroll
+    for (int j = 1; j < 6; ++j) f = (j < 2 * g.dim && d >= g.side_off[j]) ? j : f;
+    const int len = pick(g.side_len, f), so = pick(g.side_off, f);
+    const int L = (d - so) >= len, t = d - so - L * len;
+    const int partner = so + (1 - L) * len + t, mask = pick(ts.mask, f);
+    const cpx<T> cf = cface[(size_t)op_of[s] * (NI / 2) + so / 2 + t];
+    const cpx<T>* recv = slots + ((size_t)s * C + col) * NI + partner;
+    cpx<T> a = mk<T>(T(0), T(0));
+    for (int sw = 0; sw < ts.nsweeps; ++sw) {
+      if (!((mask >> sw) & 1)) continue;
+      cpx<T> gv = cf * recv[sw * slot_stride];
+      if (L == 0) gv = -gv;
+      a = a + gv;
+    }
+    srcsum[(size_t)s * per + r] = a;
+  }
+}
+
+template <class T>
+__global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int C,
+                             const c128* rg, const cpx<T>* __restrict__ srcsum, GeoDev g,
+                             long long glob, int col0) {
+  // grid: x over the entries (k, column, p) of one batch entry, flat so that
+  // every lane works, y over the batch entry b (its subdomain is uniform per
+  // workgroup); 32-bit index arithmetic
+  const int n = g.n, K = g.K, b = blockIdx.y;
+  const unsigned per = (unsigned)K * C * n;
+  const int s = mode == 2 ? 0 : ids[b];
+  const Loc sc = sub_coords(g, s);
+  for (unsigned r = blockIdx.x * blockDim.x + threadIdx.x; r < per; r += gridDim.x * blockDim.x) {
+    const int k = (int)(r / ((unsigned)C * n));
+    const int rem = (int)(r - (unsigned)k * C * n);
+    const int col = rem / n, p = rem - col * n;
     cpx<T> v = mk<T>(T(0), T(0));
     const Loc loc = block_node(g, p, k);
     if (mode == 2) {
@@ -300,48 +333,47 @@ __global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int nbatch
       for (int a = 0; a < g.dim; ++a)
         if (iface_dof(g, a, loc) == d) v.re = T(1);
     } else {
-      int s = ids[b];
-      long long G = owned_global(g, sub_coords(g, s), loc);
+      long long G = owned_global(g, sc, loc);
       if (G >= 0) v = ccast<T>(rg[(long long)col * glob + G]);
       if (mode == 1) {
-        const size_t slot_stride = (size_t)g.nsub * C * g.NI;
-        const cpx<T>* recv = slots + ((size_t)s * C + col) * g.NI;
+        const cpx<T>* a = srcsum + ((size_t)s * C + col) * g.NI;
         for (int ax = 0; ax < g.dim; ++ax) {
-          int f, L, t;
-          if (!iface_parts(g, ax, loc, f, L, t)) continue;
-          // g[layer 1] = c pair[layer 0], g[layer 0] = -c pair[layer 1]
-          const int len = pick(g.side_len, f), so = pick(g.side_off, f);
-          const int partner = so + (1 - L) * len + t, mask = pick(ts.mask, f);
-          const cpx<T> cf = cface[(size_t)op_of[s] * (g.NI / 2) + so / 2 + t];
-          cpx<T> a = mk<T>(T(0), T(0));
-          for (int sw = 0; sw < ts.nsweeps; ++sw) {
-            if (!((mask >> sw) & 1)) continue;
-            cpx<T> gv = cf * recv[sw * slot_stride + partner];
-            if (L == 0) gv = -gv;
-            a = a + gv;
-          }
-          v = v + a;
+          int d = iface_dof(g, ax, loc);
+          if (d >= 0) v = v + a[d];
         }
       }
     }
-    *dst = v;
+    panel[(size_t)b * (K + 1) * C * n + r] = v;
   }
 }
 
 template <class T>
 hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids,
                              int C, const c128* rglob, int unit_col0) {
-  long long tot = (long long)c->g.K * C * c->g.n * nbatch;
-  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
-  TraceSum ts{};
-  ts.nsweeps = c->sch.nsweeps;
-  for (int L = 0; L < c->sch.nsweeps; ++L)
-    for (int f = 0; f < 6; ++f)
-      if (c->sch.in_active[L * 6 + f]) ts.mask[f] |= (int)(1u << L);   // nsweeps <= 32
-  hipLaunchKernelGGL(k_fill_panel<T>, dim3(blocks), dim3(256), 0, c->stream,
-                     (cpx<T>*)c->d_panel, mode, d_ids, nbatch, C, rglob,
-                     (const cpx<T>*)c->d_slots, (const cpx<T>*)c->d_cface, c->d_op_of_sub, ts,
-                     c->gd, c->g.glob_nodes, unit_col0);
+  const Geometry& g = c->g;
+  if (nbatch > 65535) return hipErrorInvalidValue;
+  const long long per = (long long)g.K * C * g.n;
+  if (per >= (1LL << 31)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)std::min<long long>((per + 255) / 256, 1 << 20), nbatch);
+  if (mode == 1) {
+    // the received sources of every interface dof, summed over the sweeps
+    TraceSum ts{};
+    ts.nsweeps = c->sch.nsweeps;
+    for (int L = 0; L < c->sch.nsweeps; ++L)
+      for (int f = 0; f < 6; ++f)
+        if (c->sch.in_active[L * 6 + f]) ts.mask[f] |= (int)(1u << L);   // nsweeps <= 32
+    const long long ps = (long long)C * g.NI;
+    if (nbatch != g.nsub || ps >= (1LL << 31)) return hipErrorInvalidValue;
+    dim3 sgrid((unsigned)std::min<long long>((ps + 255) / 256, 1 << 20), g.nsub);
+    hipLaunchKernelGGL(k_source_sum<T>, sgrid, dim3(256), 0, c->stream, (cpx<T>*)c->d_srcsum,
+                       (const cpx<T>*)c->d_slots, (const cpx<T>*)c->d_cface, c->d_op_of_sub, C,
+                       ts, c->gd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fill_panel<T>, grid, dim3(256), 0, c->stream,
+                     (cpx<T>*)c->d_panel, mode, d_ids, C, rglob,
+                     (const cpx<T>*)c->d_srcsum, c->gd, g.glob_nodes, unit_col0);
   return hipGetLastError();
 }
 
@@ -381,30 +413,31 @@ hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
 template <class T>
 __global__ void k_write_owned(const cpx<T>* panel, int C, c128* glob, long long gn,
                               int accumulate, GeoDev g) {
-  const int n = g.n, K = g.K;
-  long long per = (long long)K * C * n;
-  long long tot = per * g.nsub;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int s = (int)(idx / per);
-    long long r = idx - s * per;
-    int k = (int)(r / ((long long)C * n));
-    int rem = (int)(r - (long long)k * C * n);
-    int col = rem / n, p = rem - col * n;
-    long long G = owned_global(g, sub_coords(g, s), block_node(g, p, k));
+  // grid: x over the entries (k, column, p) of one subdomain (flat), y over
+  // the subdomain; 32-bit index arithmetic
+  const int n = g.n, K = g.K, s = blockIdx.y;
+  const unsigned per = (unsigned)K * C * n;
+  const Loc sc = sub_coords(g, s);
+  for (unsigned r = blockIdx.x * blockDim.x + threadIdx.x; r < per; r += gridDim.x * blockDim.x) {
+    const int k = (int)(r / ((unsigned)C * n));
+    const int rem = (int)(r - (unsigned)k * C * n);
+    const int col = rem / n, p = rem - col * n;
+    long long G = owned_global(g, sc, block_node(g, p, k));
     if (G < 0) continue;
-    c128 v = ccast<double>(panel[(long long)s * (K + 1) * C * n + r]);
+    c128 v = ccast<double>(panel[(size_t)s * (K + 1) * C * n + r]);
     c128* dst = glob + (long long)col * gn + G;
     *dst = accumulate ? (*dst + v) : v;
   }
 }
 template <class T>
 hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate) {
-  long long tot = (long long)c->g.K * C * c->g.n * c->g.nsub;
-  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(k_write_owned<T>, dim3(blocks), dim3(256), 0, c->stream,
-                     (const cpx<T>*)c->d_panel, C, glob, c->g.glob_nodes, accumulate,
-                     c->gd);
+  const Geometry& g = c->g;
+  if (g.nsub > 65535) return hipErrorInvalidValue;
+  const long long per = (long long)g.K * C * g.n;
+  if (per >= (1LL << 31)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)std::min<long long>((per + 255) / 256, 1 << 20), g.nsub);
+  hipLaunchKernelGGL(k_write_owned<T>, grid, dim3(256), 0, c->stream,
+                     (const cpx<T>*)c->d_panel, C, glob, g.glob_nodes, accumulate, c->gd);
   return hipGetLastError();
 }
 
