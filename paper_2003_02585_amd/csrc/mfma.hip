@@ -820,8 +820,10 @@ struct FaceSet {
 // Subdomains of one launch of a step and their operators, as a kernel
 // argument: a workgroup reads its own entry with a scalar load, so every
 // address of the step is known at the start instead of after a chain of
-// dependent memory loads.
-constexpr int kStepListMax = 64;
+// dependent memory loads.  Longer anti-diagonals take several launches (the
+// 16 x 16 partitions of the benchmarks take one per step; 32 x 32 ones, in
+// the tests, two on their longer steps).
+constexpr int kStepListMax = 16;
 struct StepList {
   int n;
   int sub[kStepListMax], op[kStepListMax];
