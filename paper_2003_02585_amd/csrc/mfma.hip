@@ -795,22 +795,24 @@ hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle) {
 }
 
 // ------------------------------------------------------------ sweep step
-// One step of a sweep for the subdomains of one anti-diagonal, in two
-// launches:
-//   1. k_trace_src, trace -> source: g = [S_r, chi_r] v~ from the pairs in the
-//      step's sweep slot (g[layer 1] = c pair[layer 0], g[layer 0] =
-//      -c pair[layer 1], c = the face coefficient of the receiver), also
-//      accumulated for the final owned-node solve;
-//   2. k_sweep_step, the subdomain solve restricted to the interface layers,
-//      out = T g (+ y in the sweep that carries the sources f_ij), and in its
-//      epilogue the routing: each output pair goes into slot l' of the
-//      neighbour across its face, taken as the limit from the receiver's side
-//      (the layer on the sender's side loses the pair the sender received
-//      there).
-// Only faces that can hold a trace in this sweep enter the sum, and only
-// faces whose traces have a destination are computed.  One workgroup of 8
-// waves per (RW 16-row output tiles, 16 columns, subdomain); the waves split
-// the sum into 8/RW parts that are added in a fixed order.
+// One step of a sweep for the subdomains of one anti-diagonal, one launch
+// (2D; the 3D step below is a GEMM between two small kernels):
+//   1. trace -> source: g = [S_r, chi_r] v~ from the pairs in the step's
+//      sweep slot (g[layer 1] = c pair[layer 0], g[layer 0] = -c pair[layer 1],
+//      c = the face coefficient of the receiver), formed while the B operand
+//      is staged in LDS;
+//   2. the subdomain solve restricted to the interface layers,
+//      out = T g (+ y in the sweep that carries the sources f_ij);
+//   3. in the epilogue, the routing: each output pair goes into slot l' of
+//      the neighbour across its face, taken as the limit from the receiver's
+//      side (the layer on the sender's side loses the pair the sender
+//      received there).
+// The sources of the final owned-node solve are summed from the slots after
+// the sweeps (k_source_sum).  Only faces that can hold a trace in this sweep
+// enter the sum, and only faces whose traces have a destination are
+// computed.  One workgroup of 8 waves per (RW 16-row output tiles, 16
+// columns, subdomain); the waves split the sum into 8/RW parts that are
+// added in a fixed order.
 struct FaceSet {
   int n;                 // active faces
   int face[6];           // face ids (0:-x, 1:+x, 2:-y, 3:+y, 4:-z, 5:+z)
