@@ -48,13 +48,15 @@ struct WaveTiles {
 };
 
 // Loads under a branch make the compiler wait for every load in flight
-// before the first use; unconditional loads let it count them.  The latter
-// is faster for complex128 blocks and slower for complex64 ones (measured
-// on the 1024^2 workload: 0.91 vs 1.00 ms and 0.73 vs 0.64 ms per launch),
-// so the form follows the precision.  Unconditionally, a slice past k1
-// re-reads slice k1 - 1 and a tile past nt reads past the block's last row
-// (at most MAXT - nt tiles, kept in bounds by the spare block after the
-// inverses); neither value is used.
+// before the first use; unconditional loads let it count them.  For the X
+// tiles the counted form is faster for complex128 blocks and slower for
+// complex64 ones (measured on the 1024^2 workload: 0.91 vs 1.00 ms and 1.37
+// vs 1.20 ms per block solve), so the form follows the precision; the
+// epilogue prefetch is unconditional in both (1.20 -> 1.14 ms for
+// complex64).  Unconditionally, a slice past k1 re-reads slice k1 - 1 and a
+// tile past nt reads past the block's last row (at most MAXT - nt tiles,
+// kept in bounds by the spare block after the inverses); neither value is
+// used.
 template <class T>
 struct CountedLoads { static constexpr bool v = sizeof(T) == 8; };
 
@@ -218,12 +220,9 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      const bool ok = idx < 8 * n && c < nc;
-      if (CountedLoads<T>::v || ok) {
-        if (!ok) c = r = 0;        // unused value: keeps the load unconditional
-        fpre[q] = pb[((size_t)kn * C + c0 + c) * n + r];
-        apre[q] = ay[(size_t)face * n + r];
-      }
+      if (!(idx < 8 * n && c < nc)) c = r = 0;   // unused value: the load stays unconditional
+      fpre[q] = pb[((size_t)kn * C + c0 + c) * n + r];
+      apre[q] = ay[(size_t)face * n + r];
     }
     block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
                                     more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, red,
@@ -296,11 +295,8 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      const bool ok = idx < 8 * n && c < nc;
-      if (CountedLoads<T>::v || ok) {
-        if (!ok) r = 0;
-        apre[q] = ay[(size_t)face * n + r];
-      }
+      if (!(idx < 8 * n && c < nc)) r = 0;
+      apre[q] = ay[(size_t)face * n + r];
     }
     block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)mid * nP * nP,
                                     nsteps > 0 ? Xo + (size_t)k * nP * nP : nullptr, nP, vc,
@@ -329,12 +325,9 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      const bool ok = idx < 8 * n && c < nc;
-      if (CountedLoads<T>::v || ok) {
-        if (!ok) c = r = 0;
-        wpre[q] = pb[((size_t)k * C + c0 + c) * n + r];
-        apre[q] = ay[(size_t)face * n + r];
-      }
+      if (!(idx < 8 * n && c < nc)) c = r = 0;
+      wpre[q] = pb[((size_t)k * C + c0 + c) * n + r];
+      apre[q] = ay[(size_t)face * n + r];
     }
     block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
                                     more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, red,
