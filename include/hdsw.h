@@ -147,7 +147,8 @@ hdsw_status hdsw_apply_precond(hdsw_ctx* ctx, const hdsw_c128* r_dev,
 
 /* Global residual r = b - S x on the global grid in FP64 (b on the global
  * grid, both [nrhs][M_z][M_y][M_x] complex128 on the device), and per-RHS
- * norms ||r||_2 written to rnorm_host (nrhs doubles, may be NULL). */
+ * norms ||r||_2 written to rnorm_host (nrhs doubles, may be NULL).  r must
+ * not overlap b or x (HDSW_EINVAL). */
 hdsw_status hdsw_residual(hdsw_ctx* ctx, const hdsw_c128* b_dev,
                           const hdsw_c128* x_dev, hdsw_c128* r_dev, int nrhs,
                           double* rnorm_host);

@@ -837,6 +837,15 @@ hdsw_status residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, int nrh
                      double* rn) {
   if (c->sticky != HDSW_OK) return c->sticky;
   if (!b || !x || !r || nrhs < 1) return HDSW_EINVAL;
+  {
+    // the residual kernels read b and x through restrict pointers
+    const size_t bytes = (size_t)nrhs * c->g.glob_nodes * sizeof(c128);
+    auto overlap = [bytes](const void* p, const void* q) {
+      const char *a = (const char*)p, *d = (const char*)q;
+      return a < d + bytes && d < a + bytes;
+    };
+    if (overlap(r, b) || overlap(r, x)) return HDSW_EINVAL;
+  }
   if (c->nact > 0) return HDSW_EBUSY;  // batch slots own the workspaces
   ACHK(ensure_ws(c, std::min(nrhs, std::max(c->Cmax, 1)), false));
   for (int c0 = 0; c0 < nrhs; c0 += c->Cmax) {

@@ -311,39 +311,71 @@ __global__ void k_source_sum(cpx<T>* srcsum, const cpx<T>* __restrict__ slots,
   }
 }
 
+// Entries per thread of the panel fill and the owned-node write: their
+// global loads are issued together (unconditionally, clamped indices) before
+// any entry is written, so each thread keeps several loads in flight.
+constexpr int kFillEPT = 4;
+
 template <class T>
-__global__ void k_fill_panel(cpx<T>* panel, int mode, const int* ids, int C,
-                             const c128* rg, const cpx<T>* __restrict__ srcsum, GeoDev g,
-                             long long glob, int col0) {
+__global__ void k_fill_panel(cpx<T>* __restrict__ panel, int mode, const int* __restrict__ ids,
+                             int C, const c128* __restrict__ rg,
+                             const cpx<T>* __restrict__ srcsum, GeoDev g, long long glob,
+                             int col0) {
   // grid: x over the entries (k, column, p) of one batch entry, flat so that
   // every lane works, y over the batch entry b (its subdomain is uniform per
   // workgroup); 32-bit index arithmetic
   const int n = g.n, K = g.K, b = blockIdx.y;
-  const unsigned per = (unsigned)K * C * n;
-  const int s = mode == 2 ? 0 : ids[b];
-  const Loc sc = sub_coords(g, s);
-  for (unsigned r = blockIdx.x * blockDim.x + threadIdx.x; r < per; r += gridDim.x * blockDim.x) {
-    const int k = (int)(r / ((unsigned)C * n));
-    const int rem = (int)(r - (unsigned)k * C * n);
-    const int col = rem / n, p = rem - col * n;
-    cpx<T> v = mk<T>(T(0), T(0));
-    const Loc loc = block_node(g, p, k);
-    if (mode == 2) {
-      int d = col0 + col;
+  const unsigned per = (unsigned)K * C * n, cn = (unsigned)C * n;
+  cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
+  if (mode == 2) {
+    for (unsigned r = blockIdx.x * blockDim.x + threadIdx.x; r < per; r += gridDim.x * blockDim.x) {
+      const int k = (int)(r / cn), rem = (int)(r - (unsigned)k * cn);
+      const int col = rem / n, p = rem - col * n;
+      const Loc loc = block_node(g, p, k);
+      cpx<T> v = mk<T>(T(0), T(0));
       for (int a = 0; a < g.dim; ++a)
-        if (iface_dof(g, a, loc) == d) v.re = T(1);
-    } else {
-      long long G = owned_global(g, sc, loc);
-      if (G >= 0) v = ccast<T>(rg[(long long)col * glob + G]);
-      if (mode == 1) {
-        const cpx<T>* a = srcsum + ((size_t)s * C + col) * g.NI;
-        for (int ax = 0; ax < g.dim; ++ax) {
-          int d = iface_dof(g, ax, loc);
-          if (d >= 0) v = v + a[d];
+        if (iface_dof(g, a, loc) == col0 + col) v.re = T(1);
+      pb[r] = v;
+    }
+    return;
+  }
+  const int s = ids[b];
+  const Loc sc = sub_coords(g, s);
+  const unsigned span = blockDim.x * kFillEPT;
+  for (unsigned r0 = blockIdx.x * span + threadIdx.x; r0 < per; r0 += gridDim.x * span) {
+    c128 gv[kFillEPT];
+    long long gi[kFillEPT];                     // index into rg, -1: not owned / past the end
+#pragma unroll
+    for (int j = 0; j < kFillEPT; ++j) {
+      const unsigned r = r0 + j * blockDim.x;
+      gi[j] = -1;
+      if (r < per) {
+        const int k = (int)(r / cn), rem = (int)(r - (unsigned)k * cn);
+        const int col = rem / n, p = rem - col * n;
+        const long long G = owned_global(g, sc, block_node(g, p, k));
+        if (G >= 0) gi[j] = (long long)col * glob + G;
+      }
+      gv[j] = rg[gi[j] >= 0 ? gi[j] : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < kFillEPT; ++j) {
+      const unsigned r = r0 + j * blockDim.x;
+      if (r < per) {
+        cpx<T> v = mk<T>(T(0), T(0));
+        if (gi[j] >= 0) v = ccast<T>(gv[j]);
+        if (mode == 1) {
+          const int k = (int)(r / cn), rem = (int)(r - (unsigned)k * cn);
+          const int col = rem / n, p = rem - col * n;
+          const Loc loc = block_node(g, p, k);
+          const cpx<T>* a = srcsum + ((size_t)s * C + col) * g.NI;
+          for (int ax = 0; ax < g.dim; ++ax) {
+            int d = iface_dof(g, ax, loc);
+            if (d >= 0) v = v + a[d];
+          }
         }
+        pb[r] = v;
       }
     }
-    panel[(size_t)b * (K + 1) * C * n + r] = v;
   }
 }
 
@@ -354,7 +386,8 @@ hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids
   if (nbatch > 65535) return hipErrorInvalidValue;
   const long long per = (long long)g.K * C * g.n;
   if (per >= (1LL << 31)) return hipErrorInvalidValue;
-  dim3 grid((unsigned)std::min<long long>((per + 255) / 256, 1 << 20), nbatch);
+  const long long span = mode == 2 ? 256 : 256 * kFillEPT;
+  dim3 grid((unsigned)std::min<long long>((per + span - 1) / span, 1 << 20), nbatch);
   if (mode == 1) {
     // the received sources of every interface dof, summed over the sweeps
     TraceSum ts{};
@@ -411,22 +444,36 @@ hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
 // glob[col][G] (+)= panel on owned nodes (every global node has exactly one
 // owner, so no two threads touch the same element)
 template <class T>
-__global__ void k_write_owned(const cpx<T>* panel, int C, c128* glob, long long gn,
-                              int accumulate, GeoDev g) {
+__global__ void k_write_owned(const cpx<T>* __restrict__ panel, int C, c128* __restrict__ glob,
+                              long long gn, int accumulate, GeoDev g) {
   // grid: x over the entries (k, column, p) of one subdomain (flat), y over
   // the subdomain; 32-bit index arithmetic
   const int n = g.n, K = g.K, s = blockIdx.y;
-  const unsigned per = (unsigned)K * C * n;
+  const unsigned per = (unsigned)K * C * n, cn = (unsigned)C * n;
   const Loc sc = sub_coords(g, s);
-  for (unsigned r = blockIdx.x * blockDim.x + threadIdx.x; r < per; r += gridDim.x * blockDim.x) {
-    const int k = (int)(r / ((unsigned)C * n));
-    const int rem = (int)(r - (unsigned)k * C * n);
-    const int col = rem / n, p = rem - col * n;
-    long long G = owned_global(g, sc, block_node(g, p, k));
-    if (G < 0) continue;
-    c128 v = ccast<double>(panel[(size_t)s * (K + 1) * C * n + r]);
-    c128* dst = glob + (long long)col * gn + G;
-    *dst = accumulate ? (*dst + v) : v;
+  const cpx<T>* ps = panel + (size_t)s * (K + 1) * C * n;
+  const unsigned span = blockDim.x * kFillEPT;
+  for (unsigned r0 = blockIdx.x * span + threadIdx.x; r0 < per; r0 += gridDim.x * span) {
+    cpx<T> pv[kFillEPT];
+    c128 dv[kFillEPT];
+    long long gi[kFillEPT];                     // index into glob, -1: not owned / past the end
+#pragma unroll
+    for (int j = 0; j < kFillEPT; ++j) {
+      const unsigned r = r0 + j * blockDim.x;
+      gi[j] = -1;
+      if (r < per) {
+        const int k = (int)(r / cn), rem = (int)(r - (unsigned)k * cn);
+        const int col = rem / n, p = rem - col * n;
+        const long long G = owned_global(g, sc, block_node(g, p, k));
+        if (G >= 0) gi[j] = (long long)col * gn + G;
+      }
+      pv[j] = ps[gi[j] >= 0 ? r : 0];
+      dv[j] = mk<double>(0.0, 0.0);
+      if (accumulate) dv[j] = glob[gi[j] >= 0 ? gi[j] : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < kFillEPT; ++j)
+      if (gi[j] >= 0) glob[gi[j]] = accumulate ? dv[j] + ccast<double>(pv[j]) : ccast<double>(pv[j]);
   }
 }
 template <class T>
@@ -435,7 +482,8 @@ hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate) {
   if (g.nsub > 65535) return hipErrorInvalidValue;
   const long long per = (long long)g.K * C * g.n;
   if (per >= (1LL << 31)) return hipErrorInvalidValue;
-  dim3 grid((unsigned)std::min<long long>((per + 255) / 256, 1 << 20), g.nsub);
+  dim3 grid((unsigned)std::min<long long>((per + 256 * kFillEPT - 1) / (256 * kFillEPT), 1 << 20),
+            g.nsub);
   hipLaunchKernelGGL(k_write_owned<T>, grid, dim3(256), 0, c->stream,
                      (const cpx<T>*)c->d_panel, C, glob, g.glob_nodes, accumulate, c->gd);
   return hipGetLastError();
@@ -478,8 +526,12 @@ hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C) {
 }
 
 // r = b - S x with the global operator's coefficients formed on the fly,
-// once per node for all C columns (thread per node, columns in a loop)
-__global__ void k_residual2d(const c128* b, const c128* x, c128* r, int C,
+// once per node for all C columns (thread per node, columns in a loop).  The
+// neighbour loads are unconditional (clamped to the node itself, zeroed
+// after the load) and the pointers restrict-qualified, so the loads of
+// several columns are in flight together.
+__global__ void k_residual2d(const c128* __restrict__ b, const c128* __restrict__ x,
+                             c128* __restrict__ r, int C,
                              const c128* al, int o_nx, int o_hx, int o_ny, int o_hy,
                              const double* kap, GeoDev g, double h2, long long gn) {
   const int Mx = g.M[0], My = g.M[1];
@@ -497,15 +549,17 @@ __global__ void k_residual2d(const c128* b, const c128* x, c128* r, int C,
     c128 J = anx * any;
     c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
     const bool hl = gx > 0, hr = gx < Mx - 1, hd = gy > 0, hu = gy < My - 1;
+    const long long il = hl ? G - 1 : G, ir = hr ? G + 1 : G;
+    const long long id = hd ? G - Mx : G, iu = hu ? G + Mx : G;
+#pragma unroll 4
     for (int col = 0; col < C; ++col) {
       const c128* xc = x + (long long)col * gn;
-      c128 u = xc[G];
-      c128 z = mk<double>(0.0, 0.0);
-      c128 ul = z, ur = z, ud = z, uu = z;
-      if (hl) ul = xc[G - 1];
-      if (hr) ur = xc[G + 1];
-      if (hd) ud = xc[G - Mx];
-      if (hu) uu = xc[G + Mx];
+      const c128 z = mk<double>(0.0, 0.0);
+      c128 u = xc[G], ul = xc[il], ur = xc[ir], ud = xc[id], uu = xc[iu];
+      if (!hl) ul = z;
+      if (!hr) ur = z;
+      if (!hd) ud = z;
+      if (!hu) uu = z;
       c128 su = d * u;
       su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud);
       long long idx = (long long)col * gn + G;
@@ -515,7 +569,8 @@ __global__ void k_residual2d(const c128* b, const c128* x, c128* r, int C,
 }
 
 // 3D: 7-point operator of eq. (PML3) on the global grid
-__global__ void k_residual3d(const c128* b, const c128* x, c128* r, int C, const c128* al,
+__global__ void k_residual3d(const c128* __restrict__ b, const c128* __restrict__ x,
+                             c128* __restrict__ r, int C, const c128* al,
                              AlphaOff ao, const double* kap, GeoDev g, double h2,
                              long long gn) {
   const int* o = ao.o;
@@ -542,17 +597,21 @@ __global__ void k_residual3d(const c128* b, const c128* x, c128* r, int C, const
     c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
     const bool hl = gx > 0, hr = gx < Mx - 1, hd = gy > 0, hu = gy < My - 1, hb = gz > 0,
                hf = gz < Mz - 1;
+    const long long il = hl ? G - 1 : G, ir = hr ? G + 1 : G;
+    const long long id = hd ? G - Mx : G, iu = hu ? G + Mx : G;
+    const long long ib = hb ? G - Mxy : G, iff = hf ? G + Mxy : G;
+#pragma unroll 2
     for (int col = 0; col < C; ++col) {
       const c128* xc = x + (long long)col * gn;
-      c128 u = xc[G];
-      c128 z = mk<double>(0.0, 0.0);
-      c128 ul = z, ur = z, ud = z, uu = z, ub = z, uf = z;
-      if (hl) ul = xc[G - 1];
-      if (hr) ur = xc[G + 1];
-      if (hd) ud = xc[G - Mx];
-      if (hu) uu = xc[G + Mx];
-      if (hb) ub = xc[G - Mxy];
-      if (hf) uf = xc[G + Mxy];
+      const c128 z = mk<double>(0.0, 0.0);
+      c128 u = xc[G], ul = xc[il], ur = xc[ir], ud = xc[id], uu = xc[iu], ub = xc[ib],
+           uf = xc[iff];
+      if (!hl) ul = z;
+      if (!hr) ur = z;
+      if (!hd) ud = z;
+      if (!hu) uu = z;
+      if (!hb) ub = z;
+      if (!hf) uf = z;
       c128 su = d * u;
       su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud) +
            azr * (uf - u) - azl * (u - ub);

@@ -179,6 +179,14 @@ def test_residual_matches_oracle_operator(H):
         rt = torch.zeros_like(bt)
         norms = H.hdsw_residual(ctx, bt, xt, rt, 2)
         r = rt.cpu().numpy()
+        # r may not overlap b or x: refused before any launch (same buffer,
+        # and a view shifted by half a column)
+        gn = bt[0].numel()
+        shifted = bt.reshape(-1)[gn // 2: gn // 2 + gn].view(bt[:1].shape)
+        for rr, bb, xx in ((bt, bt, xt), (xt, bt, xt), (shifted, bt[:1], xt[:1])):
+            with pytest.raises(H.HdswError) as ei:
+                H.hdsw_residual(ctx, bb, xx, rr, 1)
+            assert ei.value.status == H.HDSW_EINVAL
     finally:
         H.hdsw_destroy(ctx)
     assert _rel(r, ref) < 1e-13
