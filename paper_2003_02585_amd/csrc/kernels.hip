@@ -526,10 +526,9 @@ hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C) {
 }
 
 // r = b - S x with the global operator's coefficients formed on the fly,
-// once per node for all C columns (thread per node, columns in a loop).  The
-// neighbour loads are unconditional (clamped to the node itself, zeroed
-// after the load) and the pointers restrict-qualified, so the loads of
-// several columns are in flight together.
+// once per node for all C columns (thread per node, columns in a loop; the
+// pointers are restrict-qualified).  Unrolling the column loop with
+// unconditional neighbour loads measured slower.
 __global__ void k_residual2d(const c128* __restrict__ b, const c128* __restrict__ x,
                              c128* __restrict__ r, int C,
                              const c128* al, int o_nx, int o_hx, int o_ny, int o_hy,
@@ -549,17 +548,15 @@ __global__ void k_residual2d(const c128* __restrict__ b, const c128* __restrict_
     c128 J = anx * any;
     c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
     const bool hl = gx > 0, hr = gx < Mx - 1, hd = gy > 0, hu = gy < My - 1;
-    const long long il = hl ? G - 1 : G, ir = hr ? G + 1 : G;
-    const long long id = hd ? G - Mx : G, iu = hu ? G + Mx : G;
-#pragma unroll 4
     for (int col = 0; col < C; ++col) {
       const c128* xc = x + (long long)col * gn;
-      const c128 z = mk<double>(0.0, 0.0);
-      c128 u = xc[G], ul = xc[il], ur = xc[ir], ud = xc[id], uu = xc[iu];
-      if (!hl) ul = z;
-      if (!hr) ur = z;
-      if (!hd) ud = z;
-      if (!hu) uu = z;
+      c128 u = xc[G];
+      c128 z = mk<double>(0.0, 0.0);
+      c128 ul = z, ur = z, ud = z, uu = z;
+      if (hl) ul = xc[G - 1];
+      if (hr) ur = xc[G + 1];
+      if (hd) ud = xc[G - Mx];
+      if (hu) uu = xc[G + Mx];
       c128 su = d * u;
       su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud);
       long long idx = (long long)col * gn + G;
@@ -597,21 +594,17 @@ __global__ void k_residual3d(const c128* __restrict__ b, const c128* __restrict_
     c128 d = mk<double>(h2 * kk * kk * J.re, h2 * kk * kk * J.im);
     const bool hl = gx > 0, hr = gx < Mx - 1, hd = gy > 0, hu = gy < My - 1, hb = gz > 0,
                hf = gz < Mz - 1;
-    const long long il = hl ? G - 1 : G, ir = hr ? G + 1 : G;
-    const long long id = hd ? G - Mx : G, iu = hu ? G + Mx : G;
-    const long long ib = hb ? G - Mxy : G, iff = hf ? G + Mxy : G;
-#pragma unroll 2
     for (int col = 0; col < C; ++col) {
       const c128* xc = x + (long long)col * gn;
-      const c128 z = mk<double>(0.0, 0.0);
-      c128 u = xc[G], ul = xc[il], ur = xc[ir], ud = xc[id], uu = xc[iu], ub = xc[ib],
-           uf = xc[iff];
-      if (!hl) ul = z;
-      if (!hr) ur = z;
-      if (!hd) ud = z;
-      if (!hu) uu = z;
-      if (!hb) ub = z;
-      if (!hf) uf = z;
+      c128 u = xc[G];
+      c128 z = mk<double>(0.0, 0.0);
+      c128 ul = z, ur = z, ud = z, uu = z, ub = z, uf = z;
+      if (hl) ul = xc[G - 1];
+      if (hr) ur = xc[G + 1];
+      if (hd) ud = xc[G - Mx];
+      if (hu) uu = xc[G + Mx];
+      if (hb) ub = xc[G - Mxy];
+      if (hf) uf = xc[G + Mxy];
       c128 su = d * u;
       su = su + axr * (ur - u) - axl * (u - ul) + ayr * (uu - u) - ayl * (u - ud) +
            azr * (uf - u) - azl * (u - ub);
