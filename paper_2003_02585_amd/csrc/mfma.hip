@@ -874,6 +874,8 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
 template <class T>
 __host__ __device__ constexpr int sweep_lcap() { return sizeof(T) == 4 ? 512 : 256; }
 constexpr int kSweepRS = 17;
+// Two-tile sweep workgroups per CU above which the four-tile form is used
+constexpr int kSweepRounds = 2;
 
 // The sum runs face by face over the active input faces.  For each face the
 // B operand is staged in LDS already split for the two real MFMAs of the
@@ -1331,13 +1333,6 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
   // batches (measured: complex64 8 -> 10 shortens the step by 5%, 12 is
   // slower again; complex128 4 -> 5 by 4%)
   constexpr int KB = sizeof(T) == 4 ? 10 : 5;
-  // two 16-row tiles per workgroup, the sum split in four (measured best of
-  // one, two and four tiles at the 1024^2 workload)
-  constexpr int RW = 2;
-  const int nrt = (nout + 16 * RW - 1) / (16 * RW);
-  // LDS: the staged operand pairs, or the KH partial tiles of the sum
-  size_t lds = std::max<size_t>((size_t)2 * LMAX * kSweepRS, (size_t)(8 / RW) * 16 * 16 * RW) *
-               sizeof(cpx<T>);
   // the step's subdomains in launches of at most kStepListMax
   for (int b0 = 0; b0 < cnt; b0 += kStepListMax) {
     StepList sl{};
@@ -1346,12 +1341,27 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
       sl.sub[i] = c->sch.step_subs[off + b0 + i];
       sl.op[i] = c->op_of_sub[sl.sub[i]];
     }
-    dim3 grid(8 * ((nrt + 7) / 8) * sl.n, Cp / 16, 1);
-    hipLaunchKernelGGL((k_sweep_step<T, KB, RW>), grid, dim3(512), lds, c->stream,
-                       (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_cface, (cpx<T>*)c->d_slots,
-                       (const cpx<T>*)c->d_y, sl, L, C, fin, fout, nout, L == 0 ? 1 : 0, LMAX,
-                       nsub_chunks, c->gd);
-    hipError_t e = hipGetLastError();
+    // RW 16-row tiles per workgroup, the sum split in 8 / RW: two tiles
+    // while the step is latency-bound (few workgroups per CU), four once
+    // two-tile workgroups would take more than kSweepRounds rounds of the
+    // 256 CUs (measured: two tiles best at 1024^2 with 16 RHS, four at
+    // 2048^2 with 64 RHS)
+    auto launch = [&](auto rw) -> hipError_t {
+      constexpr int RW = decltype(rw)::value;
+      const int nrt = (nout + 16 * RW - 1) / (16 * RW);
+      // LDS: the staged operand pairs, or the KH partial tiles of the sum
+      size_t lds = std::max<size_t>((size_t)2 * LMAX * kSweepRS,
+                                    (size_t)(8 / RW) * 16 * 16 * RW) * sizeof(cpx<T>);
+      dim3 grid(8 * ((nrt + 7) / 8) * sl.n, Cp / 16, 1);
+      hipLaunchKernelGGL((k_sweep_step<T, KB, RW>), grid, dim3(512), lds, c->stream,
+                         (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_cface,
+                         (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_y, sl, L, C, fin, fout, nout,
+                         L == 0 ? 1 : 0, LMAX, nsub_chunks, c->gd);
+      return hipGetLastError();
+    };
+    const long long wg2 = 8LL * (((nout + 31) / 32 + 7) / 8) * sl.n * (Cp / 16);
+    hipError_t e = wg2 > kSweepRounds * 256 ? launch(std::integral_constant<int, 4>{})
+                                            : launch(std::integral_constant<int, 2>{});
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
