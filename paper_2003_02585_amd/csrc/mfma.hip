@@ -83,22 +83,26 @@ __device__ __forceinline__ void mv_load(WaveTiles<T, MAXT, KSB>& w, const cpx<T>
   }
 }
 
-template <class T, int MAXT, int KSB>
+// NG groups of 8 columns: every X tile loaded feeds NG pairs of MFMAs
+template <class T, int MAXT, int KSB, int NG>
 __device__ __forceinline__ void mv_mfma(const WaveTiles<T, MAXT, KSB>& w,
-                                        typename MF<T>::v4 (&acc)[MAXT], const cpx<T>* vb,
+                                        typename MF<T>::v4 (&acc)[MAXT][NG], const cpx<T>* vb,
                                         int kb0, int k1, int nt, int kk, int cc, int part) {
 #pragma unroll
   for (int q = 0; q < KSB; ++q) {
     const int ks = kb0 + q;
     if (ks < k1) {
-      const cpx<T> vv = vb[(4 * ks + kk) * 8 + cc];
-      const T b1 = part ? vv.im : vv.re;
-      const T b2 = part ? vv.re : -vv.im;
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) {
-        if (t < nt) {
-          acc[t] = MF<T>::mfma(w.x[q][t].re, b1, acc[t]);
-          acc[t] = MF<T>::mfma(w.x[q][t].im, b2, acc[t]);
+      for (int gq = 0; gq < NG; ++gq) {
+        const cpx<T> vv = vb[(4 * ks + kk) * 8 * NG + gq * 8 + cc];
+        const T b1 = part ? vv.im : vv.re;
+        const T b2 = part ? vv.re : -vv.im;
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+          if (t < nt) {
+            acc[t][gq] = MF<T>::mfma(w.x[q][t].re, b1, acc[t][gq]);
+            acc[t][gq] = MF<T>::mfma(w.x[q][t].im, b2, acc[t][gq]);
+          }
         }
       }
     }
@@ -134,47 +138,52 @@ __device__ inline WaveGeo wave_geo(int nP, int wave, int lane) {
 // X_k; on exit it holds the first batch of Xnext (if not null).  Every wave
 // leaves its part of the sum (rows of its half, a quarter of the columns of
 // X_k) in red[kq]; ends with the block synchronized, the parts complete.
-template <class T, int MAXT, int KSB, int NW>
+template <class T, int MAXT, int KSB, int NW, int NG>
 __device__ __forceinline__ void block_product(WaveTiles<T, MAXT, KSB>& tiles, const WaveGeo& wg,
                                               const cpx<T>* __restrict__ Xk,
                                               const cpx<T>* __restrict__ Xnext, int nP,
                                               const cpx<T>* vc, cpx<T>* red, int lane) {
   typedef typename MF<T>::v4 v4;
-  v4 acc[MAXT];
+  v4 acc[MAXT][NG];
 #pragma unroll
-  for (int t = 0; t < MAXT; ++t) acc[t] = v4{T(0), T(0), T(0), T(0)};
-  mv_mfma<T, MAXT, KSB>(tiles, acc, vc, wg.k0, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
+  for (int t = 0; t < MAXT; ++t)
+#pragma unroll
+    for (int gq = 0; gq < NG; ++gq) acc[t][gq] = v4{T(0), T(0), T(0), T(0)};
+  mv_mfma<T, MAXT, KSB, NG>(tiles, acc, vc, wg.k0, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
   for (int kb = wg.k0 + KSB; kb < wg.k1; kb += KSB) {
     mv_load<T, MAXT, KSB>(tiles, Xk, nP, wg.t0, wg.nt, kb, wg.k1, wg.kk, wg.rr);
-    mv_mfma<T, MAXT, KSB>(tiles, acc, vc, kb, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
+    mv_mfma<T, MAXT, KSB, NG>(tiles, acc, vc, kb, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
   }
   if (Xnext) mv_load<T, MAXT, KSB>(tiles, Xnext, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk, wg.rr);
-  T* dst = reinterpret_cast<T*>(red + (size_t)wg.kq * 8 * nP);
+  T* dst = reinterpret_cast<T*>(red + (size_t)wg.kq * 8 * NG * nP);
 #pragma unroll
   for (int t = 0; t < MAXT; ++t)
     if (t < wg.nt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int row = 16 * (wg.t0 + t) + MF<T>::row(lane, i);
-        dst[2 * (row * 8 + wg.cc) + wg.part] = acc[t][i];
-      }
+      for (int gq = 0; gq < NG; ++gq)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          int row = 16 * (wg.t0 + t) + MF<T>::row(lane, i);
+          dst[2 * (row * 8 * NG + gq * 8 + wg.cc) + wg.part] = acc[t][gq][i];
+        }
   lds_barrier();
 }
 
-// Entry rc = row * 8 + column of the last block product: its NW / 2 parts
+// Entry rc = row * 8 NG + column of the last block product: its NW / 2 parts
 // added in a fixed order, so the result does not depend on timing.
-template <class T, int NW>
+template <class T, int NW, int NG>
 __device__ __forceinline__ cpx<T> prod_y(const cpx<T>* red, int nP, int rc) {
   cpx<T> y = red[rc];
 #pragma unroll
-  for (int q = 1; q < NW / 2; ++q) y = y + red[(size_t)q * 8 * nP + rc];
+  for (int q = 1; q < NW / 2; ++q) y = y + red[(size_t)q * 8 * NG * nP + rc];
   return y;
 }
 
 // ------------------------------------------------------------ solve A
 // EPT epilogue elements per thread have their global operands prefetched
-// before the block product (EPT * threads >= 8 n is checked at launch).
-template <class T, int MAXT, int KSB, int NW, int EPT>
+// before the block product (EPT * threads >= 8 NG n is checked at launch).
+// A workgroup owns 8 NG columns of one batch entry and one chain.
+template <class T, int MAXT, int KSB, int NW, int EPT, int NG>
 __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict__ X,
                                                        size_t xstride,
                                                        const cpx<T>* __restrict__ coefT,
@@ -186,23 +195,24 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
   const int n = g.n, nP = g.nP, K = g.K, mid = g.mid;
   const int b = blockIdx.y, half = blockIdx.z;
   if (b >= nbatch) return;
-  const int c0 = blockIdx.x * 8, nc = min(8, C - c0);
+  constexpr int NCOL = 8 * NG;                    // columns of the workgroup
+  const int c0 = blockIdx.x * NCOL, nc = min(NCOL, C - c0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cpx<T>* vb0 = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* vb1 = vb0 + 8 * nP;
-  cpx<T>* red = vb1 + 8 * nP;                     // NW / 2 parts of a product
+  cpx<T>* vb1 = vb0 + NCOL * nP;
+  cpx<T>* red = vb1 + NCOL * nP;                  // NW / 2 parts of a product
   const int op = ops[b];
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
   cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
   const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
-  for (int idx = tid; idx < 16 * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
+  for (int idx = tid; idx < 2 * NCOL * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
   lds_barrier();
   int k = half ? K - 1 : 0;
   const int nsteps = half ? K - 1 - mid : mid;
-  for (int idx = tid; idx < 8 * n; idx += NT) {
+  for (int idx = tid; idx < NCOL * n; idx += NT) {
     int c = idx / n, r = idx - c * n;
-    if (c < nc) vb0[r * 8 + c] = pb[((size_t)k * C + c0 + c) * n + r];
+    if (c < nc) vb0[r * NCOL + c] = pb[((size_t)k * C + c0 + c) * n + r];
   }
   WaveTiles<T, MAXT, KSB> tiles;
   mv_load<T, MAXT, KSB>(tiles, Xo + (size_t)k * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk,
@@ -220,22 +230,22 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (!(idx < 8 * n && c < nc)) c = r = 0;   // unused value: the load stays unconditional
+      if (!(idx < NCOL * n && c < nc)) c = r = 0;   // unused value: the load stays unconditional
       fpre[q] = pb[((size_t)kn * C + c0 + c) * n + r];
       apre[q] = ay[(size_t)face * n + r];
     }
-    block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
+    block_product<T, MAXT, KSB, NW, NG>(tiles, wg, Xo + (size_t)k * nP * nP,
                                     more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, red,
                                     lane);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (idx < 8 * n && c < nc) {
-        cpx<T> y = prod_y<T, NW>(red, nP, r * 8 + c);
+      if (idx < NCOL * n && c < nc) {
+        cpx<T> y = prod_y<T, NW, NG>(red, nP, r * NCOL + c);
         pb[((size_t)k * C + c0 + c) * n + r] = y;
         cpx<T> nxt = fpre[q] - apre[q] * y;
-        if (more) vn[r * 8 + c] = nxt;
+        if (more) vn[r * NCOL + c] = nxt;
         else if (half == 0)   // scratch line K: f_m - B_m w_{m-1}
           pb[((size_t)K * C + c0 + c) * n + r] = nxt;
       }
@@ -249,7 +259,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
 }
 
 // ------------------------------------------------------------ solve B
-template <class T, int MAXT, int KSB, int NW, int EPT>
+template <class T, int MAXT, int KSB, int NW, int EPT, int NG>
 __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict__ X,
                                                        size_t xstride,
                                                        const cpx<T>* __restrict__ coefT,
@@ -261,23 +271,24 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
   const int n = g.n, nP = g.nP, K = g.K, mid = g.mid;
   const int b = blockIdx.y, half = blockIdx.z;
   if (b >= nbatch) return;
-  const int c0 = blockIdx.x * 8, nc = min(8, C - c0);
+  constexpr int NCOL = 8 * NG;                    // columns of the workgroup
+  const int c0 = blockIdx.x * NCOL, nc = min(NCOL, C - c0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cpx<T>* vb0 = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* vb1 = vb0 + 8 * nP;
-  cpx<T>* red = vb1 + 8 * nP;                     // NW / 2 parts of a product
+  cpx<T>* vb1 = vb0 + NCOL * nP;
+  cpx<T>* red = vb1 + NCOL * nP;                  // NW / 2 parts of a product
   const int op = ops[b];
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
   cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
   const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
-  for (int idx = tid; idx < 16 * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
+  for (int idx = tid; idx < 2 * NCOL * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
   lds_barrier();
   // middle line: v = (f_m - B_m w_{m-1}) - B_{m+1} v_{m+1}
-  for (int idx = tid; idx < 8 * n; idx += NT) {
+  for (int idx = tid; idx < NCOL * n; idx += NT) {
     int c = idx / n, r = idx - c * n;
     if (c < nc)
-      vb0[r * 8 + c] = pb[((size_t)K * C + c0 + c) * n + r] -
+      vb0[r * NCOL + c] = pb[((size_t)K * C + c0 + c) * n + r] -
                        ay[(size_t)(mid + 1) * n + r] * pb[((size_t)(mid + 1) * C + c0 + c) * n + r];
   }
   WaveTiles<T, MAXT, KSB> tiles;
@@ -295,20 +306,20 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (!(idx < 8 * n && c < nc)) r = 0;
+      if (!(idx < NCOL * n && c < nc)) r = 0;
       apre[q] = ay[(size_t)face * n + r];
     }
-    block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)mid * nP * nP,
+    block_product<T, MAXT, KSB, NW, NG>(tiles, wg, Xo + (size_t)mid * nP * nP,
                                     nsteps > 0 ? Xo + (size_t)k * nP * nP : nullptr, nP, vc,
                                     red, lane);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (idx < 8 * n && c < nc) {
-        cpx<T> x = prod_y<T, NW>(red, nP, r * 8 + c);
+      if (idx < NCOL * n && c < nc) {
+        cpx<T> x = prod_y<T, NW, NG>(red, nP, r * NCOL + c);
         if (half == 0) pb[((size_t)mid * C + c0 + c) * n + r] = x;
-        vn[r * 8 + c] = apre[q] * x;
+        vn[r * NCOL + c] = apre[q] * x;
       }
     }
     lds_barrier();
@@ -325,21 +336,21 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (!(idx < 8 * n && c < nc)) c = r = 0;
+      if (!(idx < NCOL * n && c < nc)) c = r = 0;
       wpre[q] = pb[((size_t)k * C + c0 + c) * n + r];
       apre[q] = ay[(size_t)face * n + r];
     }
-    block_product<T, MAXT, KSB, NW>(tiles, wg, Xo + (size_t)k * nP * nP,
+    block_product<T, MAXT, KSB, NW, NG>(tiles, wg, Xo + (size_t)k * nP * nP,
                                     more ? Xo + (size_t)kn * nP * nP : nullptr, nP, vc, red,
                                     lane);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
       int c = idx / n, r = idx - c * n;
-      if (idx < 8 * n && c < nc) {
-        cpx<T> x = wpre[q] - prod_y<T, NW>(red, nP, r * 8 + c);
+      if (idx < NCOL * n && c < nc) {
+        cpx<T> x = wpre[q] - prod_y<T, NW, NG>(red, nP, r * NCOL + c);
         pb[((size_t)k * C + c0 + c) * n + r] = x;
-        if (more) vn[r * 8 + c] = apre[q] * x;
+        if (more) vn[r * NCOL + c] = apre[q] * x;
       }
     }
     lds_barrier();
@@ -351,10 +362,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
 }
 
 template <class T>
-static int solve_nw(int nP) {
-  // as many waves as the LDS allows: (2 + NW/2) vectors of 8 x nP complex
+static int solve_nw(int nP, int NG) {
+  // as many waves as the LDS allows: (2 + NW/2) vectors of 8 NG x nP complex
   size_t e = sizeof(cpx<T>);
-  auto fits = [&](int nw) { return (size_t)(2 + nw / 2) * 8 * nP * e <= 160 * 1024; };
+  auto fits = [&](int nw) { return (size_t)(2 + nw / 2) * 8 * NG * nP * e <= 160 * 1024; };
   if (fits(8)) return 8;
   if (fits(4)) return 4;
   return 0;
@@ -367,33 +378,33 @@ struct SolveKSB {
   static constexpr int v = sizeof(T) == 4 ? (MAXT <= 5 ? 5 : 2) : (MAXT == 5 ? 3 : 2);
 };
 
-template <class T, int MAXT, int NW>
+template <class T, int MAXT, int NW, int NG>
 static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
-  constexpr int EPT = 2048 / (NW * 64);
+  constexpr int EPT = 2048 * NG / (NW * 64);
   const Geometry& g = c->g;
-  if (8 * g.n > EPT * NW * 64) return hipErrorInvalidValue;
-  dim3 grid((C + 7) / 8, nbatch, 2);
-  size_t lds = (size_t)(2 + NW / 2) * 8 * g.nP * sizeof(cpx<T>);
+  if (8 * NG * g.n > EPT * NW * 64) return hipErrorInvalidValue;
+  dim3 grid((C + 8 * NG - 1) / (8 * NG), nbatch, 2);
+  size_t lds = (size_t)(2 + NW / 2) * 8 * NG * g.nP * sizeof(cpx<T>);
   size_t xstride = (size_t)g.K * g.nP * g.nP;
-  hipLaunchKernelGGL((k_solve_fwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT>), grid, dim3(NW * 64), lds,
+  hipLaunchKernelGGL((k_solve_fwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT, NG>), grid, dim3(NW * 64), lds,
                      c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
                      c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve_bwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT>), grid, dim3(NW * 64), lds,
+  hipLaunchKernelGGL((k_solve_bwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT, NG>), grid, dim3(NW * 64), lds,
                      c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
                      c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
   return hipGetLastError();
 }
 
-template <class T, int NW>
+template <class T, int NW, int NG>
 static hipError_t launch_solve_nw(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
   const int nMt = c->g.nP / 16;
   const int th = (nMt + 1) / 2;
-  if (th <= 2) return launch_solve_t<T, 2, NW>(c, nbatch, d_ops, C);
-  if (th <= 3) return launch_solve_t<T, 3, NW>(c, nbatch, d_ops, C);
-  if (th <= 5) return launch_solve_t<T, 5, NW>(c, nbatch, d_ops, C);
-  if (th <= 8) return launch_solve_t<T, 8, NW>(c, nbatch, d_ops, C);
+  if (th <= 2) return launch_solve_t<T, 2, NW, NG>(c, nbatch, d_ops, C);
+  if (th <= 3) return launch_solve_t<T, 3, NW, NG>(c, nbatch, d_ops, C);
+  if (th <= 5) return launch_solve_t<T, 5, NW, NG>(c, nbatch, d_ops, C);
+  if (th <= 8) return launch_solve_t<T, 8, NW, NG>(c, nbatch, d_ops, C);
   return hipErrorInvalidValue;   // nP <= 256 (checked at setup): at most 8 tiles per half
 }
 
@@ -415,9 +426,18 @@ hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) 
                                  c->d_zero_int, 1, 1, C);
     return hipErrorInvalidValue;
   }
-  const int nw = solve_nw<T>(c->g.nP);
-  if (nw == 8) return launch_solve_nw<T, 8>(c, nbatch, d_ops, C);
-  if (nw == 4) return launch_solve_nw<T, 4>(c, nbatch, d_ops, C);
+  // complex64: 16 columns per workgroup once 8-column workgroups would take
+  // more than two rounds of the 256 CUs (throughput-bound: every X tile then
+  // feeds twice the MFMAs); 8 while the chain latency dominates.  complex128
+  // keeps 8 (16 would not fit the register file)
+  if constexpr (sizeof(T) == 4) {
+    const long long wg8 = (long long)((C + 7) / 8) * nbatch * 2;
+    if (C >= 16 && wg8 > 2 * 256 && solve_nw<T>(c->g.nP, 2) == 8)
+      return launch_solve_nw<T, 8, 2>(c, nbatch, d_ops, C);
+  }
+  const int nw = solve_nw<T>(c->g.nP, 1);
+  if (nw == 8) return launch_solve_nw<T, 8, 1>(c, nbatch, d_ops, C);
+  if (nw == 4) return launch_solve_nw<T, 4, 1>(c, nbatch, d_ops, C);
   return hipErrorInvalidValue;
 }
 

@@ -232,6 +232,36 @@ def test_batch_invariance(H):
         assert np.array_equal(batch[i], alone[i])
 
 
+def test_wide_batch_block_solve(H):
+    # 1024 subdomains x 20 RHS puts the complex64 block solve on 16-column
+    # workgroups (a full group and a ragged one of 4); one RHS alone runs on
+    # 8-column workgroups.  Columns of an MFMA product are independent, so
+    # the two agree bit for bit, and the batch stays at the complex64 bar
+    c = _case(256, 4, (32, 32), 1.5, nrhs=20, seed=5)
+    sol = O.SubdomainSolvers(c["part"])
+    pick = [0, 17, 19]
+    ref = [O.ddm_apply(c["prob"], c["part"], c["b"][i], rounds=1, solvers=sol) for i in pick]
+    _say("wide batch block solve (complex64, 20 RHS, 32x32)")
+    ctx = _ctx(H, c, precision=H.HDSW_MIXED)
+    try:
+        r = torch.from_numpy(c["b"]).cuda()
+        z = torch.zeros_like(r)
+        H.hdsw_apply_precond(ctx, r, z, 20)
+        alone = []
+        for i in pick:
+            zi = torch.zeros_like(r[i:i + 1])
+            H.hdsw_apply_precond(ctx, r[i:i + 1].contiguous(), zi, 1)
+            alone.append(zi.cpu().numpy()[0])
+        batch = z.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    e = _rel([batch[i] for i in pick], ref)
+    _say(f"  rel diff {e:.3e}")
+    assert e < 2e-4
+    for j, i in enumerate(pick):
+        assert np.array_equal(batch[i], alone[j])
+
+
 def _golden(name):
     import os
     p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"samples_{name}.npz")
