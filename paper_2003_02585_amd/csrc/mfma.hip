@@ -55,18 +55,26 @@ struct WaveTiles {
 // epilogue prefetch is unconditional in both (1.20 -> 1.14 ms for
 // complex64).  Unconditionally, a slice past k1 re-reads slice k1 - 1 and a
 // tile past nt reads past the block's last row (at most MAXT - nt tiles,
-// kept in bounds by the spare block after the inverses); neither value is
-// used.
-template <class T>
-struct CountedLoads { static constexpr bool v = sizeof(T) == 8; };
+// kept in bounds by the spare block after the inverses); neither value
+// reaches a result.
+//
+// complex64 with 8-column workgroups double-buffers the batches instead: the
+// second batch is loaded while the first one's MFMAs run, with counted loads
+// and unconditional MFMAs (a slice past k1 gets a zero vector operand), 1.14
+// -> 1.09 ms per block solve on the 1024^2 workload; the other forms would
+// spill with a second buffer.
+template <class T, int NG>
+struct DoubleBuf { static constexpr bool v = sizeof(T) == 4 && NG == 1; };
+template <class T, int NG>
+struct CountedLoads { static constexpr bool v = sizeof(T) == 8 || DoubleBuf<T, NG>::v; };
 
-template <class T, int MAXT, int KSB>
+template <class T, int MAXT, int KSB, int NG>
 __device__ __forceinline__ void mv_load(WaveTiles<T, MAXT, KSB>& w, const cpx<T>* __restrict__ Xb,
                                         int nP, int t0, int nt, int kb0, int k1, int kk, int rr) {
   const cpx<T>* base = Xb + (size_t)(t0 * 16 + rr);
 #pragma unroll
   for (int q = 0; q < KSB; ++q) {
-    if constexpr (CountedLoads<T>::v) {
+    if constexpr (CountedLoads<T, NG>::v) {
       const int ks = max(0, min(kb0 + q, k1 - 1));
       const cpx<T>* xc = base + (size_t)(4 * ks + kk) * nP;
 #pragma unroll
@@ -104,6 +112,32 @@ __device__ __forceinline__ void mv_mfma(const WaveTiles<T, MAXT, KSB>& w,
             acc[t][gq] = MF<T>::mfma(w.x[q][t].im, b2, acc[t][gq]);
           }
         }
+      }
+    }
+  }
+}
+
+// The same with every MFMA issued (double-buffered form): slices past k1
+// multiply a zero vector operand, tiles past nt accumulate rows never stored
+template <class T, int MAXT, int KSB, int NG>
+__device__ __forceinline__ void mv_mfma_all(const WaveTiles<T, MAXT, KSB>& w,
+                                            typename MF<T>::v4 (&acc)[MAXT][NG],
+                                            const cpx<T>* vb, int kb0, int k1, int kk, int cc,
+                                            int part) {
+#pragma unroll
+  for (int q = 0; q < KSB; ++q) {
+    const int ks = kb0 + q;
+    const bool ok = ks < k1;
+    const int ksc = ok ? ks : k1 - 1;
+#pragma unroll
+    for (int gq = 0; gq < NG; ++gq) {
+      const cpx<T> vv = vb[(4 * ksc + kk) * 8 * NG + gq * 8 + cc];
+      const T b1 = ok ? (part ? vv.im : vv.re) : T(0);
+      const T b2 = ok ? (part ? vv.re : -vv.im) : T(0);
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        acc[t][gq] = MF<T>::mfma(w.x[q][t].re, b1, acc[t][gq]);
+        acc[t][gq] = MF<T>::mfma(w.x[q][t].im, b2, acc[t][gq]);
       }
     }
   }
@@ -149,12 +183,27 @@ __device__ __forceinline__ void block_product(WaveTiles<T, MAXT, KSB>& tiles, co
   for (int t = 0; t < MAXT; ++t)
 #pragma unroll
     for (int gq = 0; gq < NG; ++gq) acc[t][gq] = v4{T(0), T(0), T(0), T(0)};
-  mv_mfma<T, MAXT, KSB, NG>(tiles, acc, vc, wg.k0, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
-  for (int kb = wg.k0 + KSB; kb < wg.k1; kb += KSB) {
-    mv_load<T, MAXT, KSB>(tiles, Xk, nP, wg.t0, wg.nt, kb, wg.k1, wg.kk, wg.rr);
-    mv_mfma<T, MAXT, KSB, NG>(tiles, acc, vc, kb, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
+  if constexpr (DoubleBuf<T, NG>::v) {
+    WaveTiles<T, MAXT, KSB> tb;
+    for (int kb = wg.k0; kb < wg.k1; kb += 2 * KSB) {
+      const bool second = kb + KSB < wg.k1;
+      if (second)
+        mv_load<T, MAXT, KSB, NG>(tb, Xk, nP, wg.t0, wg.nt, kb + KSB, wg.k1, wg.kk, wg.rr);
+      mv_mfma_all<T, MAXT, KSB, NG>(tiles, acc, vc, kb, wg.k1, wg.kk, wg.cc, wg.part);
+      if (kb + 2 * KSB < wg.k1)
+        mv_load<T, MAXT, KSB, NG>(tiles, Xk, nP, wg.t0, wg.nt, kb + 2 * KSB, wg.k1, wg.kk, wg.rr);
+      if (second)
+        mv_mfma_all<T, MAXT, KSB, NG>(tb, acc, vc, kb + KSB, wg.k1, wg.kk, wg.cc, wg.part);
+    }
+  } else {
+    mv_mfma<T, MAXT, KSB, NG>(tiles, acc, vc, wg.k0, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
+    for (int kb = wg.k0 + KSB; kb < wg.k1; kb += KSB) {
+      mv_load<T, MAXT, KSB, NG>(tiles, Xk, nP, wg.t0, wg.nt, kb, wg.k1, wg.kk, wg.rr);
+      mv_mfma<T, MAXT, KSB, NG>(tiles, acc, vc, kb, wg.k1, wg.nt, wg.kk, wg.cc, wg.part);
+    }
   }
-  if (Xnext) mv_load<T, MAXT, KSB>(tiles, Xnext, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk, wg.rr);
+  if (Xnext)
+    mv_load<T, MAXT, KSB, NG>(tiles, Xnext, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk, wg.rr);
   T* dst = reinterpret_cast<T*>(red + (size_t)wg.kq * 8 * NG * nP);
 #pragma unroll
   for (int t = 0; t < MAXT; ++t)
@@ -215,7 +264,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
     if (c < nc) vb0[r * NCOL + c] = pb[((size_t)k * C + c0 + c) * n + r];
   }
   WaveTiles<T, MAXT, KSB> tiles;
-  mv_load<T, MAXT, KSB>(tiles, Xo + (size_t)k * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk,
+  mv_load<T, MAXT, KSB, NG>(tiles, Xo + (size_t)k * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1, wg.kk,
                         wg.rr);
   lds_barrier();
   cpx<T>* vc = vb0;
@@ -292,7 +341,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
                        ay[(size_t)(mid + 1) * n + r] * pb[((size_t)(mid + 1) * C + c0 + c) * n + r];
   }
   WaveTiles<T, MAXT, KSB> tiles;
-  mv_load<T, MAXT, KSB>(tiles, Xo + (size_t)mid * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1,
+  mv_load<T, MAXT, KSB, NG>(tiles, Xo + (size_t)mid * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1,
                         wg.kk, wg.rr);
   lds_barrier();
   cpx<T>* vc = vb0;
