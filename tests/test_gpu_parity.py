@@ -262,6 +262,47 @@ def test_wide_batch_block_solve(H):
         assert np.array_equal(batch[i], alone[j])
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_degenerate_inputs(H, prec):
+    # a zero right-hand side has the zero solution: its relative residual is
+    # taken as 0, so it converges at iteration 0 with x = 0 exactly and leaves
+    # the other columns of its batch unchanged; no columns at all is an
+    # argument error of every entry point
+    c = _case(48, 8, (3, 3), 1.5, nrhs=3, seed=29)
+    _say(f"degenerate inputs {prec}")
+    p = H.HDSW_FP64 if prec == "fp64" else H.HDSW_MIXED
+    ctx = _ctx(H, c, precision=p, tol=1e-10)
+    try:
+        f = c["f"].copy()
+        f[1] = 0
+        ft = torch.from_numpy(f).cuda()
+        xb = torch.full_like(ft, 7.0)
+        info, _ = H.hdsw_solve(ctx, ft, xb, 3)
+        alone = []
+        for j in (0, 2):
+            xj = torch.zeros_like(ft[j:j + 1])
+            H.hdsw_solve(ctx, ft[j:j + 1].contiguous(), xj, 1)
+            alone.append(xj.cpu().numpy()[0])
+        r0 = torch.zeros((1,) + c["b"].shape[1:], dtype=torch.complex128, device="cuda")
+        z0 = torch.full_like(r0, 7.0)
+        H.hdsw_apply_precond(ctx, r0, z0, 1)
+        for call in (lambda: H.hdsw_solve(ctx, ft, xb, 0),
+                     lambda: H.hdsw_apply_precond(ctx, r0, z0, 0),
+                     lambda: H.hdsw_residual(ctx, r0, z0, torch.zeros_like(r0), 0)):
+            with pytest.raises(H.HdswError) as ei:
+                call()
+            assert ei.value.status == H.HDSW_EINVAL
+        x = xb.cpu().numpy()
+        zz = z0.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    _say(f"  iterations {[i for i, _ in info]}")
+    assert info[1] == (0, 0.0)
+    assert not np.any(x[1])
+    assert not np.any(zz)
+    assert np.array_equal(x[0], alone[0]) and np.array_equal(x[2], alone[1])
+
+
 def _golden(name):
     import os
     p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"samples_{name}.npz")
