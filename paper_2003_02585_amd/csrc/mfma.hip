@@ -23,10 +23,12 @@
 //   B: middle  x_m = X_m (f_m - B_m w_{m-1} - B_{m+1} v_{m+1})
 //      top     x_k = w_k - X_k B_{k+1} x_{k+1}        k = m-1 .. 0
 //      bottom  x_k = v_k - X_k B_k x_{k-1}            k = m+1 .. K-1
-// Every block product is a complex matrix times 8 complex columns on the
-// matrix cores: with X = Xr + i Xi and V = Vr + i Vi,
+// Every block product is a complex matrix times groups of 8 complex columns
+// on the matrix cores (one group per workgroup, two for complex64 batches
+// with many workgroups): with X = Xr + i Xi and V = Vr + i Vi,
 //   [Yr | Yi] = Xr [Vr | Vi] + Xi [-Vi | Vr],
-// two real 16x16x4 MFMAs per 16-row tile and 4-deep slice of the sum.
+// two real 16x16x4 MFMAs per 16-row tile, column group and 4-deep slice of
+// the sum.
 #include "hdsw_internal.hpp"
 #include "mfma_ops.hpp"
 

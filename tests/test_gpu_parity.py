@@ -70,6 +70,7 @@ DDM_CASES = [
     (45, 4, (3, 5), 1.5, 2),     # odd and unequal: n = 23, K = 17
     (256, 4, (32, 32), None, 1), # partition of the largest serving grids
     (256, 4, (32, 32), 1.5, 2),
+    (416, 8, (2, 2), None, 1),   # n = 224: complex128 block solve on 4 waves
 ]
 
 
@@ -92,7 +93,10 @@ def test_fp64_ddm_matches_oracle(H, N, W, P, layer, rounds):
     assert e < 1e-10
 
 
-@pytest.mark.parametrize("N,W,P,layer,rounds", DDM_CASES[:4])
+@pytest.mark.parametrize("N,W,P,layer,rounds", DDM_CASES[:4] + [
+    (384, 8, (2, 2), 1.5, 1),    # n = 208: 13 row tiles, 8-tile waves, odd split
+    (56, 5, (2, 7), 1.5, 1),     # ragged
+])
 def test_mixed_ddm_close_to_oracle(H, N, W, P, layer, rounds):
     c = _case(N, W, P, layer, nrhs=2)
     sol = O.SubdomainSolvers(c["part"])
