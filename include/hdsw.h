@@ -28,7 +28,11 @@
  *    the slowest index: [nrhs][grid].
  *  - Device pointers must come from hipMalloc (or a caching allocator on
  *    top of it) on the context's device; they stay owned by the caller and
- *    must stay valid until the call returns.
+ *    must stay valid until the call returns.  Every entry point checks each
+ *    array with hipPointerGetAttributes before any kernel runs: host memory
+ *    (pinned or not), another device's memory, or an allocation too small
+ *    for the stated nrhs (checked against the allocation that contains the
+ *    pointer) returns HDSW_EINVAL and leaves the context usable.
  *  - Every call is ordered on the context's stream and returns when its
  *    work is complete.  One host thread per context; separate contexts may
  *    be used concurrently on separate streams.
@@ -84,6 +88,18 @@ typedef struct {
                      m > 0: right-preconditioned GMRES(m), FP64 Arnoldi     */
   int dedup;      /* share factors between identical subdomain operators    */
   size_t hbm_budget; /* bytes for factors plus workspaces; 0 = no limit      */
+  /* Device allocator hooks (both or neither; NULL = hipMalloc / hipFree).
+   * Every device allocation of the context -- factors, interface responses,
+   * workspaces -- is made by dev_alloc(bytes, alloc_ctx), which returns
+   * device memory of the context's device usable on the context's stream,
+   * aligned to 256 bytes, or NULL (the call then returns HDSW_ENOMEM); each
+   * is released by dev_free(ptr, alloc_ctx), at the latest in hdsw_destroy.
+   * Lets a framework's caching allocator own the memory pool.  The hooks are
+   * called from the calling thread only, and must not call into the
+   * library. */
+  void* (*dev_alloc)(size_t bytes, void* alloc_ctx);
+  void (*dev_free)(void* ptr, void* alloc_ctx);
+  void* alloc_ctx;
 } hdsw_options;
 
 typedef struct {
@@ -92,7 +108,8 @@ typedef struct {
 } hdsw_solve_info;
 
 /* Fills *opt with the defaults: HDSW_MIXED, rounds 1, pml_R 1e-16,
- * tol 1e-10, max_iter 30, gmres_m 0, dedup 1, no budget. */
+ * tol 1e-10, max_iter 30, gmres_m 0, dedup 1, no budget, no allocator
+ * hooks. */
 void hdsw_default_options(hdsw_options* opt);
 
 /* Validates the problem, builds the partition, the per-subdomain layer
@@ -106,8 +123,8 @@ void hdsw_default_options(hdsw_options* opt);
  *   stream     : hipStream_t to order all work on (NULL = default stream).
  *   out        : receives the context; unchanged on failure.
  * Errors: EINVAL (dim not 2/3, n % nsub != 0, nonpositive sizes, W < 1,
- * non-finite or nonpositive k, h <= 0, bad options, NULL pointers), ENOMEM
- * (budget or allocation), EDEVICE. */
+ * non-finite or nonpositive k, h <= 0, bad options, only one allocator
+ * hook, NULL pointers), ENOMEM (budget or allocation), EDEVICE. */
 hdsw_status hdsw_setup(const hdsw_grid* grid, const double* kappa_host,
                        const hdsw_partition* part, int pml_width,
                        const hdsw_options* opt, void* stream, hdsw_ctx** out);

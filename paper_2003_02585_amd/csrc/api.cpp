@@ -34,6 +34,9 @@ void hdsw_default_options(hdsw_options* o) {
   o->gmres_m = 0;
   o->dedup = 1;
   o->hbm_budget = 0;
+  o->dev_alloc = nullptr;
+  o->dev_free = nullptr;
+  o->alloc_ctx = nullptr;
 }
 
 hdsw_status hdsw_setup(const hdsw_grid* grid, const double* kappa_host,
@@ -48,6 +51,13 @@ hdsw_status hdsw_setup(const hdsw_grid* grid, const double* kappa_host,
   }
 }
 
+// An exception other than bad_alloc out of a context call leaves the
+// context in an unknown state: the error is made sticky.
+static hdsw_status fail_ctx(hdsw_ctx* ctx) {
+  ctx->sticky = HDSW_EDEVICE;
+  return HDSW_EDEVICE;
+}
+
 hdsw_status hdsw_factor(hdsw_ctx* ctx) {
   if (!ctx) return HDSW_EINVAL;
   try {
@@ -55,7 +65,7 @@ hdsw_status hdsw_factor(hdsw_ctx* ctx) {
   } catch (const std::bad_alloc&) {
     return HDSW_ENOMEM;
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -68,7 +78,7 @@ hdsw_status hdsw_solve(hdsw_ctx* ctx, const hdsw_c128* f, hdsw_c128* x, int nrhs
   } catch (const std::bad_alloc&) {
     return HDSW_ENOMEM;
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -80,7 +90,7 @@ hdsw_status hdsw_apply_precond(hdsw_ctx* ctx, const hdsw_c128* r, hdsw_c128* z, 
   } catch (const std::bad_alloc&) {
     return HDSW_ENOMEM;
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -92,7 +102,7 @@ hdsw_status hdsw_residual(hdsw_ctx* ctx, const hdsw_c128* b, const hdsw_c128* x,
                           reinterpret_cast<const hdsw::c128*>(x),
                           reinterpret_cast<hdsw::c128*>(r), nrhs, rnorm);
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -125,7 +135,7 @@ hdsw_status hdsw_batch_reserve(hdsw_ctx* ctx, int capacity) {
   } catch (const std::bad_alloc&) {
     return HDSW_ENOMEM;
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -134,7 +144,7 @@ hdsw_status hdsw_batch_add(hdsw_ctx* ctx, const hdsw_c128* f, int nrhs, int* slo
   try {
     return hdsw::batch_add(ctx, reinterpret_cast<const hdsw::c128*>(f), nrhs, slots);
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -143,7 +153,7 @@ hdsw_status hdsw_batch_step(hdsw_ctx* ctx) {
   try {
     return hdsw::batch_step(ctx);
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -152,7 +162,7 @@ hdsw_status hdsw_batch_wait(hdsw_ctx* ctx, double* rel_residual) {
   try {
     return hdsw::batch_wait(ctx, rel_residual);
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -161,7 +171,7 @@ hdsw_status hdsw_batch_ready(hdsw_ctx* ctx) {
   try {
     return hdsw::batch_ready(ctx);
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 
@@ -170,7 +180,7 @@ hdsw_status hdsw_batch_take(hdsw_ctx* ctx, int slot, hdsw_c128* x) {
   try {
     return hdsw::batch_take(ctx, slot, reinterpret_cast<hdsw::c128*>(x));
   } catch (...) {
-    return HDSW_EDEVICE;
+    return fail_ctx(ctx);
   }
 }
 

@@ -676,7 +676,7 @@ __global__ void k_plane_rhs(cpx<T>* panel, int nbatch, int C, int k, int fwd,
     int b = (int)(idx / per);
     long long r = idx - b * per;
     int p = (int)(r % n);
-    cpx<T>* base = panel + (long long)b * (K + 1) * per;
+    cpx<T>* base = panel + (long long)b * g.PL * per;
     const cpx<T>* az = coefT + (size_t)ops[b] * cstride + o_az;
     cpx<T> v;
     if (fwd) {
@@ -717,11 +717,11 @@ hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int
       a.sAz = (long long)K * nn;
       a.B = P + (long long)K * per;
       a.ldb = n;
-      a.sb = (long long)(K + 1) * per;
+      a.sb = (long long)g.PL * per;
       a.sBz = 0;
       a.C = P + (long long)k * per;
       a.ldc = n;
-      a.sc = (long long)(K + 1) * per;
+      a.sc = (long long)g.PL * per;
       a.sCz = 0;
       a.cpb = C;
       a.ids = ids;

@@ -146,11 +146,21 @@ static uint64_t fnv1a(const void* data, size_t n) {
 }
 
 // ------------------------------------------------------------ memory
+// Every device allocation of a context goes through these two: the caller's
+// allocator hooks when hdsw_options sets them (so a framework's caching
+// allocator can own the memory), hipMalloc / hipFree otherwise.
+static void raw_free(const hdsw_ctx* c, void* p) {
+  if (c->opt.dev_free) c->opt.dev_free(p, c->opt.alloc_ctx);
+  else (void)hipFree(p);
+}
 static hdsw_status dev_alloc(hdsw_ctx* c, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
   if (c->opt.hbm_budget && c->alloc_bytes + bytes > c->opt.hbm_budget) return HDSW_ENOMEM;
-  if (hipMalloc(p, bytes) != hipSuccess) {
+  if (c->opt.dev_alloc) {
+    *p = c->opt.dev_alloc(bytes, c->opt.alloc_ctx);
+    if (!*p) return HDSW_ENOMEM;
+  } else if (hipMalloc(p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
     return HDSW_ENOMEM;
@@ -164,12 +174,48 @@ static void dev_free(hdsw_ctx* c, void* p) {
   for (size_t i = 0; i < c->bufs.size(); ++i) {
     if (c->bufs[i].p == p) {
       c->alloc_bytes -= c->bufs[i].bytes;
-      (void)hipFree(p);
+      raw_free(c, p);
       c->bufs.erase(c->bufs.begin() + i);
       return;
     }
   }
 }
+static void free_all(hdsw_ctx* c) {
+  for (auto& b : c->bufs) raw_free(c, b.p);
+  c->bufs.clear();
+  c->alloc_bytes = 0;
+}
+
+// A caller's array: device memory of the context's device (hipMalloc or an
+// allocator on top of it, or managed memory) that holds `bytes` from p.
+// Host memory, pinned or not, and other devices' memory are rejected before
+// any kernel sees the pointer.  The size is checked against the allocation
+// that contains p (a caching allocator's block: the bound is that block).
+hdsw_status check_dev_ptr(const hdsw_ctx* c, const void* p, size_t bytes) {
+  if (!p) return HDSW_EINVAL;
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // not known to the runtime: plain host memory
+    return HDSW_EINVAL;
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) return HDSW_EINVAL;
+  if (a.device != c->device) return HDSW_EINVAL;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) == hipSuccess) {
+    const char* lo = (const char*)base;
+    if ((const char*)p < lo || (size_t)((const char*)p - lo) + bytes > size) return HDSW_EINVAL;
+  } else {
+    (void)hipGetLastError();
+  }
+  return HDSW_OK;
+}
+#define PCHK(ptr, bytes)                                   \
+  do {                                                     \
+    hdsw_status s_ = check_dev_ptr(c, (ptr), (bytes));     \
+    if (s_ != HDSW_OK) return s_;                          \
+  } while (0)
 #define ACHK(expr)                         \
   do {                                     \
     hdsw_status s_ = (expr);               \
@@ -253,6 +299,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   if (opt->rounds < 1 || opt->rounds > 4 || !(opt->pml_R > 0 && opt->pml_R < 1) ||
       !(opt->tol > 0) || opt->max_iter < 0 || opt->gmres_m < 0 || opt->gmres_m > 200)
     return HDSW_EINVAL;
+  if (!opt->dev_alloc != !opt->dev_free) return HDSW_EINVAL;   // both hooks or neither
   hdsw_ctx* c = new (std::nothrow) hdsw_ctx();
   if (!c) return HDSW_ENOMEM;
   Geometry& g = c->g;
@@ -290,6 +337,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   }
   g.nP = (g.n + 15) / 16 * 16;
   g.mid = g.K / 2;
+  g.PL = g.K + 2;
   // the 2D block solver keeps an nP-long vector per column in LDS; 3D plane
   // blocks go through the dense-block path
   if (g.dim == 2 && g.nP > 256) {
@@ -342,6 +390,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   d.nsub = g.nsub;
   d.nP = g.nP;
   d.mid = g.mid;
+  d.PL = g.PL;
   for (int a = 0; a < 3; ++a) {
     d.N[a] = g.N[a];
     d.P[a] = g.P[a];
@@ -417,7 +466,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   }
 
   auto fail = [&](hdsw_status st) {
-    for (auto& b : c->bufs) (void)hipFree(b.p);
+    free_all(c);
     delete c;
     return st;
   };
@@ -626,7 +675,7 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
   // interface-to-interface response T = P_I S^{-1} P_I^T of every distinct
   // operator: block solves with unit sources on the interface dofs
   const size_t e = sizeof(cpx<T>);
-  size_t per_col = (size_t)(g.K + 1) * g.n * e;
+  size_t per_col = (size_t)g.PL * g.n * e;
   size_t budget = (size_t)1 << 31;
   int ct = (int)std::min<size_t>(g.NI, std::max<size_t>(1, budget / per_col));
   void* tmp = nullptr;
@@ -701,7 +750,7 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     dst = decltype(dst)(p);               \
   } while (0)
     size_t iface = (size_t)g.nsub * C * g.NI * e;
-    WALLOC(c->d_panel, (size_t)g.nsub * (g.K + 1) * C * g.n * e);
+    WALLOC(c->d_panel, (size_t)g.nsub * g.PL * C * g.n * e);
     WALLOC(c->d_slots, iface * c->sch.nsweeps);
     WALLOC(c->d_srcsum, iface);
     WALLOC(c->d_y, iface);
@@ -723,11 +772,14 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     WALLOC(c->d_norm, (size_t)C * sizeof(double));
     c->Cmax = C;
   }
-  if (need_gmres && (c->gm_m != c->opt.gmres_m || !c->d_V || C > c->Cmax)) {
+  // the Krylov basis is sized for the workspaces' column count: regrow it
+  // whenever the workspaces grew since it was allocated
+  if (need_gmres && (c->gm_m != c->opt.gmres_m || !c->d_V || c->gm_cols < c->Cmax)) {
     dev_free(c, c->d_V);
     dev_free(c, c->d_Z);
     dev_free(c, c->d_dots);
     c->d_V = c->d_Z = c->d_dots = nullptr;
+    c->gm_cols = 0;
     int m = c->opt.gmres_m;
     void* p;
     hdsw_status st;
@@ -735,6 +787,7 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     WALLOC(c->d_Z, (size_t)m * c->Cmax * g.glob_nodes * sizeof(c128));
     WALLOC(c->d_dots, (size_t)2 * (m + 1) * c->Cmax * sizeof(c128));
     c->gm_m = m;
+    c->gm_cols = c->Cmax;
   }
   return HDSW_OK;
 }
@@ -805,7 +858,7 @@ static size_t max_cols(hdsw_ctx* c) {
   if (!c->opt.hbm_budget) return 1u << 30;
   const Geometry& g = c->g;
   size_t e = elt(c);
-  size_t per_col = (size_t)g.nsub * (g.K + 1) * g.n * e +
+  size_t per_col = (size_t)g.nsub * g.PL * g.n * e +
                    (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 4 : 2)) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
@@ -821,6 +874,8 @@ hdsw_status apply_precond(hdsw_ctx* c, const c128* r, c128* z, int nrhs) {
   if (c->sticky != HDSW_OK) return c->sticky;
   if (!c->factored) return HDSW_ENOTFACTORED;
   if (!r || !z || nrhs < 1) return HDSW_EINVAL;
+  PCHK(r, (size_t)nrhs * c->g.glob_nodes * sizeof(c128));
+  PCHK(z, (size_t)nrhs * c->g.glob_nodes * sizeof(c128));
   if (c->nact > 0) return HDSW_EBUSY;  // batch slots own the workspaces
   int chunk = (int)std::min<size_t>(nrhs, max_cols(c));
   if (chunk < 1) return HDSW_ENOMEM;
@@ -837,6 +892,9 @@ hdsw_status residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r, int nrh
                      double* rn) {
   if (c->sticky != HDSW_OK) return c->sticky;
   if (!b || !x || !r || nrhs < 1) return HDSW_EINVAL;
+  PCHK(b, (size_t)nrhs * c->g.glob_nodes * sizeof(c128));
+  PCHK(x, (size_t)nrhs * c->g.glob_nodes * sizeof(c128));
+  PCHK(r, (size_t)nrhs * c->g.glob_nodes * sizeof(c128));
   {
     // the residual kernels read b and x through restrict pointers
     const size_t bytes = (size_t)nrhs * c->g.glob_nodes * sizeof(c128);
@@ -907,6 +965,8 @@ hdsw_status solve(hdsw_ctx* c, const c128* f, c128* x, int nrhs, hdsw_solve_info
   if (c->sticky != HDSW_OK) return c->sticky;
   if (!c->factored) return HDSW_ENOTFACTORED;
   if (!f || !x || nrhs < 1) return HDSW_EINVAL;
+  PCHK(f, (size_t)nrhs * c->g.int_nodes * sizeof(c128));
+  PCHK(x, (size_t)nrhs * c->g.int_nodes * sizeof(c128));
   if (c->nact > 0) return HDSW_EBUSY;  // batch slots own the workspaces
   int chunk = (int)std::min<size_t>(nrhs, max_cols(c));
   if (chunk < 1) return HDSW_ENOMEM;
@@ -977,6 +1037,7 @@ hdsw_status batch_add(hdsw_ctx* c, const c128* f, int nrhs, int* slots) {
   if (c->sticky != HDSW_OK) return c->sticky;
   if (c->batch_cap == 0) return HDSW_ENOTFACTORED;
   if (!f || !slots || nrhs < 1) return HDSW_EINVAL;
+  PCHK(f, (size_t)nrhs * c->g.int_nodes * sizeof(c128));
   if (c->nact + nrhs > c->batch_cap) return HDSW_EBUSY;
   const size_t gn = (size_t)c->g.glob_nodes;
   const int c0 = c->nact;
@@ -1047,6 +1108,7 @@ hdsw_status batch_take(hdsw_ctx* c, int slot, c128* x) {
   if (c->sticky != HDSW_OK) return c->sticky;
   if (c->batch_cap == 0) return HDSW_ENOTFACTORED;
   if (slot < 0 || slot >= c->batch_cap || c->col_of_slot[slot] < 0) return HDSW_EINVAL;
+  if (x) PCHK(x, (size_t)c->g.int_nodes * sizeof(c128));
   const Geometry& g = c->g;
   const size_t gn = (size_t)g.glob_nodes;
   int col = c->col_of_slot[slot];
@@ -1096,7 +1158,7 @@ void destroy(hdsw_ctx* c) {
       if (e) (void)hipEventDestroy(e);
     pools().erase(it);
   }
-  for (auto& b : c->bufs) (void)hipFree(b.p);
+  free_all(c);
   delete c;
 }
 

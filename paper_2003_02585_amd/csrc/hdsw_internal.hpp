@@ -109,6 +109,7 @@ struct Geometry {
   int n = 1, K = 1;
   int nP = 16;                 // n rounded up to a multiple of 16 (MFMA tiles)
   int mid = 0;                 // middle line of the twisted factorization
+  int PL = 3;                  // panel lines per subdomain: K block lines + 2 scratch lines
   long long sub_nodes = 1;     // nodes of one extended subdomain
   long long glob_nodes = 1;    // nodes of the global grid
   long long int_nodes = 1;     // interior nodes
@@ -128,7 +129,7 @@ struct Geometry {
 
 // Device-side view of the geometry (plain struct passed by value).
 struct GeoDev {
-  int dim, W, n, K, NI, nsub, nP, mid;
+  int dim, W, n, K, NI, nsub, nP, mid, PL;
   int N[3], P[3], na[3], ne[3], M[3];
   int side_len[6], side_off[6];
 };
@@ -230,7 +231,7 @@ struct hdsw_ctx {
 
   // workspaces sized for Cmax columns
   int Cmax = 0;
-  void* d_panel = nullptr;          // [nsub][K+1][C][n] (line K: scratch)
+  void* d_panel = nullptr;          // [nsub][PL][C][n], PL = K + 2 (lines K, K+1: scratch)
   void* d_slots = nullptr;          // [nsweeps][nsub][C][NI]
   void* d_g = nullptr;              // 3D: [nsub][Cp][padded k] sources of a step
   void* d_srcsum = nullptr;         // [nsub][C][NI] received sources, summed over sweeps
@@ -246,6 +247,7 @@ struct hdsw_ctx {
   int part_blocks = 0;
   // GMRES workspace
   int gm_m = 0;
+  int gm_cols = 0;                  // columns V, Z and dots are sized for
   hdsw::c128* d_V = nullptr;        // [m+1][C][glob]
   hdsw::c128* d_Z = nullptr;        // [m][C][glob]
   hdsw::c128* d_dots = nullptr;     // [m+1][C]

@@ -326,7 +326,7 @@ __global__ void k_fill_panel(cpx<T>* __restrict__ panel, int mode, const int* __
   // workgroup); 32-bit index arithmetic
   const int n = g.n, K = g.K, b = blockIdx.y;
   const unsigned per = (unsigned)K * C * n, cn = (unsigned)C * n;
-  cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
+  cpx<T>* pb = panel + (size_t)b * g.PL * C * n;
   if (mode == 2) {
     for (unsigned r = blockIdx.x * blockDim.x + threadIdx.x; r < per; r += gridDim.x * blockDim.x) {
       const int k = (int)(r / cn), rem = (int)(r - (unsigned)k * cn);
@@ -427,7 +427,7 @@ __global__ void k_extract_iface(const cpx<T>* panel, int nbatch, int C, cpx<T>* 
     const int p = g.dim == 2 ? loc.x : loc.y * g.ne[0] + loc.x;
     const int k = g.dim == 2 ? loc.y : loc.z;
     dst[b * dst_sb + (long long)col * dst_ld + i] =
-        panel[(((long long)b * (g.K + 1) + k) * C + col) * g.n + p];
+        panel[(((long long)b * g.PL + k) * C + col) * g.n + p];
   }
 }
 template <class T>
@@ -451,7 +451,7 @@ __global__ void k_write_owned(const cpx<T>* __restrict__ panel, int C, c128* __r
   const int n = g.n, K = g.K, s = blockIdx.y;
   const unsigned per = (unsigned)K * C * n, cn = (unsigned)C * n;
   const Loc sc = sub_coords(g, s);
-  const cpx<T>* ps = panel + (size_t)s * (K + 1) * C * n;
+  const cpx<T>* ps = panel + (size_t)s * g.PL * C * n;
   const unsigned span = blockDim.x * kFillEPT;
   for (unsigned r0 = blockIdx.x * span + threadIdx.x; r0 < per; r0 += gridDim.x * span) {
     cpx<T> pv[kFillEPT];

@@ -3,7 +3,11 @@
 // RHS columns.  Orthogonalisation is classical Gram-Schmidt applied twice
 // (the dots of one pass are independent, so each pass is one batched
 // reduction on the device); the small Hessenberg least-squares problem of
-// every column is reduced by Givens rotations on the host.
+// every column is reduced by Givens rotations on the host.  A column whose
+// residual estimate meets the tolerance inside a cycle takes its update from
+// the Arnoldi steps up to that point only (later steps, run for the other
+// columns, do not enter it), so its result and iteration count are those of
+// the same column solved alone.
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -35,6 +39,7 @@ hdsw_status gmres_cols(hdsw_ctx* c, int C, std::vector<int>& iters, std::vector<
   const int m = c->opt.gmres_m;
   const long long gn = g.glob_nodes;
   const size_t vec = (size_t)C * gn;
+  if (C > c->gm_cols || C > c->Cmax) return HDSW_EINVAL;   // basis sized for fewer columns
   c128* V = c->d_V;
   c128* Z = c->d_Z;
   c128* dots = c->d_dots;                          // [(m+1)][C]
@@ -47,6 +52,9 @@ hdsw_status gmres_cols(hdsw_ctx* c, int C, std::vector<int>& iters, std::vector<
       gv((size_t)C * (m + 1));
   std::vector<c128> hbuf((size_t)(m + 1) * C), cbuf((size_t)(m + 1) * C);
   int total = 0;
+  // per column: Arnoldi steps of the current cycle that enter its update,
+  // and the iteration count at which its estimate met the tolerance
+  std::vector<int> kcol(C, 0), done_at(C, -1);
   auto h_at = [&](int col, int i, int j) -> cd& { return H[((size_t)col * (m + 1) + i) * m + j]; };
   while (true) {
     HCHK(launch_residual(c, c->d_bg, c->d_xg, c->d_rg, C));
@@ -58,7 +66,7 @@ hdsw_status gmres_cols(hdsw_ctx* c, int C, std::vector<int>& iters, std::vector<
     std::vector<char> active(C, 0);
     for (int j = 0; j < C; ++j) {
       rel[j] = bn[j] > 0 ? nrm[j] / bn[j] : 0.0;
-      if (iters[j] < 0 && rel[j] <= c->opt.tol) iters[j] = total;
+      if (iters[j] < 0 && rel[j] <= c->opt.tol) iters[j] = done_at[j] >= 0 ? done_at[j] : total;
       if (iters[j] < 0) {
         all = false;
         active[j] = 1;
@@ -75,6 +83,7 @@ hdsw_status gmres_cols(hdsw_ctx* c, int C, std::vector<int>& iters, std::vector<
     HCHK(launch_scale(c, V, c->d_rg, c->d_norm, C));
     int kused = 0;
     std::vector<char> done(C, 0);
+    for (int j = 0; j < C; ++j) done_at[j] = -1;
     for (int k = 0; k < m; ++k) {
       c128* Vk = V + (size_t)k * vec;
       c128* Zk = Z + (size_t)k * vec;
@@ -127,7 +136,11 @@ hdsw_status gmres_cols(hdsw_ctx* c, int C, std::vector<int>& iters, std::vector<
         gv[(size_t)j * (m + 1) + k + 1] = -std::conj(ss) * gk;
         gv[(size_t)j * (m + 1) + k] = cc * gk;
         double est = std::abs(gv[(size_t)j * (m + 1) + k + 1]);
-        if (active[j] && !done[j] && (est <= c->opt.tol * bn[j] || nrm[j] == 0.0)) done[j] = 1;
+        if (active[j] && !done[j] && (est <= c->opt.tol * bn[j] || nrm[j] == 0.0)) {
+          done[j] = 1;
+          kcol[j] = k + 1;
+          done_at[j] = total;
+        }
         if (active[j] && !done[j]) all_done = false;
       }
       if (all_done || total >= c->opt.max_iter) break;
@@ -135,10 +148,11 @@ hdsw_status gmres_cols(hdsw_ctx* c, int C, std::vector<int>& iters, std::vector<
     // x += Z y, y = H^{-1} g (upper triangular, per column)
     for (int j = 0; j < C; ++j) {
       std::vector<cd> y(kused, 0.0);
+      const int kj = done[j] ? kcol[j] : kused;
       if (active[j]) {
-        for (int i = kused - 1; i >= 0; --i) {
+        for (int i = kj - 1; i >= 0; --i) {
           cd s = gv[(size_t)j * (m + 1) + i];
-          for (int l = i + 1; l < kused; ++l) s -= h_at(j, i, l) * y[l];
+          for (int l = i + 1; l < kj; ++l) s -= h_at(j, i, l) * y[l];
           cd d = h_at(j, i, i);
           y[i] = std::abs(d) > 0 ? s / d : 0.0;
         }

@@ -19,7 +19,9 @@
 // Solve with the stored inverses, two launches:
 //   A: top     w_k = X_k (f_k - B_k w_{k-1})          k = 0 .. m-1
 //      bottom  v_k = X_k (f_k - B_{k+1} v_{k+1})      k = K-1 .. m+1
-//      (the top chain leaves f_m - B_m w_{m-1} in a scratch line)
+//      (the top chain leaves f_m - B_m w_{m-1} in scratch line K, the
+//      bottom chain B_{m+1} v_{m+1} in scratch line K + 1, so launch B never
+//      reads a line that one of its chains overwrites)
 //   B: middle  x_m = X_m (f_m - B_m w_{m-1} - B_{m+1} v_{m+1})
 //      top     x_k = w_k - X_k B_{k+1} x_{k+1}        k = m-1 .. 0
 //      bottom  x_k = v_k - X_k B_k x_{k-1}            k = m+1 .. K-1
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
   const int op = ops[b];
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
-  cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
+  cpx<T>* pb = panel + (size_t)b * g.PL * C * n;
   const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
   for (int idx = tid; idx < 2 * NCOL * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
   lds_barrier();
@@ -299,6 +301,8 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
         if (more) vn[r * NCOL + c] = nxt;
         else if (half == 0)   // scratch line K: f_m - B_m w_{m-1}
           pb[((size_t)K * C + c0 + c) * n + r] = nxt;
+        else                  // scratch line K + 1: B_{m+1} v_{m+1}
+          pb[((size_t)(K + 1) * C + c0 + c) * n + r] = apre[q] * y;
       }
     }
     lds_barrier();
@@ -331,16 +335,19 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
   const int op = ops[b];
   const cpx<T>* Xo = X + (size_t)op * xstride;
   const cpx<T>* ay = coefT + (size_t)op * cstride + (size_t)K * (n + 1);
-  cpx<T>* pb = panel + (size_t)b * (K + 1) * C * n;
+  cpx<T>* pb = panel + (size_t)b * g.PL * C * n;
   const WaveGeo wg = wave_geo<NW>(nP, wave, lane);
   for (int idx = tid; idx < 2 * NCOL * nP; idx += NT) vb0[idx] = mk<T>(T(0), T(0));
   lds_barrier();
-  // middle line: v = (f_m - B_m w_{m-1}) - B_{m+1} v_{m+1}
+  // middle line: v = (f_m - B_m w_{m-1}) - B_{m+1} v_{m+1}, both terms from
+  // the scratch lines the forward launch left.  Line m + 1 itself is not
+  // read: the bottom chain of this launch overwrites it with x_{m+1}, and
+  // nothing orders the two chains' workgroups.
   for (int idx = tid; idx < NCOL * n; idx += NT) {
     int c = idx / n, r = idx - c * n;
     if (c < nc)
       vb0[r * NCOL + c] = pb[((size_t)K * C + c0 + c) * n + r] -
-                       ay[(size_t)(mid + 1) * n + r] * pb[((size_t)(mid + 1) * C + c0 + c) * n + r];
+                          pb[((size_t)(K + 1) * C + c0 + c) * n + r];
   }
   WaveTiles<T, MAXT, KSB> tiles;
   mv_load<T, MAXT, KSB, NG>(tiles, Xo + (size_t)mid * nP * nP, nP, wg.t0, wg.nt, wg.k0, wg.k1,
@@ -945,8 +952,10 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
 template <class T>
 __host__ __device__ constexpr int sweep_lcap() { return sizeof(T) == 4 ? 512 : 256; }
 constexpr int kSweepRS = 17;
-// Two-tile sweep workgroups per CU above which the four-tile form is used
-constexpr int kSweepRounds = 2;
+// Two-tile workgroups per 16-column group of a step above which the
+// four-tile form is used (the 1024^2 workload's largest steps, 8 subdomains
+// of 40 row-tile workgroups, stay at two tiles)
+constexpr int kSweepRows = 320;
 
 // The sum runs face by face over the active input faces.  For each face the
 // B operand is staged in LDS already split for the two real MFMAs of the
@@ -1412,11 +1421,14 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
       sl.sub[i] = c->sch.step_subs[off + b0 + i];
       sl.op[i] = c->op_of_sub[sl.sub[i]];
     }
-    // RW 16-row tiles per workgroup, the sum split in 8 / RW: two tiles
-    // while the step is latency-bound (few workgroups per CU), four once
-    // two-tile workgroups would take more than kSweepRounds rounds of the
-    // 256 CUs (measured: two tiles best at 1024^2 with 16 RHS, four at
-    // 2048^2 with 64 RHS)
+    // RW 16-row tiles per workgroup, the sum split in 8 / RW parts.  The
+    // split fixes the order in which a column's partial sums are added, so
+    // it is chosen from the step's shape only (rows and subdomains), never
+    // from the column count: a column's result is then the same whichever
+    // columns share the launch.  Two tiles while one column group of
+    // two-tile workgroups fits in kSweepRows workgroups, four on larger
+    // steps (measured: two tiles best at 1024^2 with 16 RHS, four on the
+    // large steps at 2048^2 with 64 RHS)
     auto launch = [&](auto rw) -> hipError_t {
       constexpr int RW = decltype(rw)::value;
       const int nrt = (nout + 16 * RW - 1) / (16 * RW);
@@ -1430,9 +1442,9 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
                          L == 0 ? 1 : 0, LMAX, nsub_chunks, c->gd);
       return hipGetLastError();
     };
-    const long long wg2 = 8LL * (((nout + 31) / 32 + 7) / 8) * sl.n * (Cp / 16);
-    hipError_t e = wg2 > kSweepRounds * 256 ? launch(std::integral_constant<int, 4>{})
-                                            : launch(std::integral_constant<int, 2>{});
+    const long long wg2 = 8LL * (((nout + 31) / 32 + 7) / 8) * sl.n;
+    hipError_t e = wg2 > kSweepRows ? launch(std::integral_constant<int, 4>{})
+                                    : launch(std::integral_constant<int, 2>{});
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -38,11 +38,17 @@ class hdsw_partition(ctypes.Structure):
     _fields_ = [("nsub", ctypes.c_int * 3)]
 
 
+DEV_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEV_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class hdsw_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("rounds", ctypes.c_int),
                 ("pml_R", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("gmres_m", ctypes.c_int),
-                ("dedup", ctypes.c_int), ("hbm_budget", ctypes.c_size_t)]
+                ("dedup", ctypes.c_int), ("hbm_budget", ctypes.c_size_t),
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class hdsw_solve_info(ctypes.Structure):
@@ -138,12 +144,52 @@ def hdsw_default_options(**kw):
     return o
 
 
-def _dev_ptr(t, what):
+# Per context: interior and global node counts, the reserved batch capacity
+# and the allocator hooks that must outlive it (keyed by the handle's value).
+_CTX = {}
+
+
+def _dev_ptr(t, what, need=None):
+    """Device address of a contiguous complex128 GPU tensor holding at least
+    `need` elements."""
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128
             and t.is_contiguous()):
         raise TypeError(f"{what} must be a contiguous complex128 tensor on the GPU")
+    if need is not None and t.numel() < need:
+        raise ValueError(f"{what} holds {t.numel()} elements, the call needs {need}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _sizes(ctx):
+    info = _CTX.get(ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx)
+    if info is None:
+        raise ValueError("unknown or destroyed context")
+    return info
+
+
+def torch_allocator_hooks(device=None):
+    """Allocator hooks for hdsw_options that take every device allocation of
+    a context from torch's caching allocator (uint8 tensors held until the
+    library frees them).  Returns (dev_alloc, dev_free, live): pass the first
+    two to hdsw_default_options(dev_alloc=..., dev_free=...); `live` maps
+    each pointer the library holds to its tensor."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    live = {}
+
+    def _alloc(nbytes, _ctx):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        except RuntimeError:
+            return None
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(ptr, _ctx):
+        live.pop(int(ptr), None)
+
+    return DEV_ALLOC_FN(_alloc), DEV_FREE_FN(_free), live
 
 
 def hdsw_setup(kappa, h, nsub, pml_width, options=None, stream=None):
@@ -170,6 +216,11 @@ def hdsw_setup(kappa, h, nsub, pml_width, options=None, stream=None):
                          ctypes.byref(p), int(pml_width), ctypes.byref(opt), s,
                          ctypes.byref(ctx))
     _check(st, "hdsw_setup")
+    nint = int(np.prod(kappa.shape))
+    nglob = int(np.prod([int(x) + 2 * int(pml_width) for x in kappa.shape]))
+    # the hooks' ctypes objects must live as long as the context
+    _CTX[ctx.value] = dict(nint=nint, nglob=nglob, cap=0,
+                           hooks=(opt.dev_alloc, opt.dev_free))
     return ctx
 
 
@@ -181,21 +232,24 @@ def hdsw_solve(ctx, f, x, nrhs, raise_on_noconv=True):
     """f, x: complex128 GPU tensors [nrhs][interior grid].  Returns a list of
     (iters, rel_residual) per RHS and the status."""
     info = (hdsw_solve_info * int(nrhs))()
-    st = _lib.hdsw_solve(ctx, _dev_ptr(f, "f"), _dev_ptr(x, "x"), int(nrhs), info)
+    n = _sizes(ctx)["nint"] * int(nrhs)
+    st = _lib.hdsw_solve(ctx, _dev_ptr(f, "f", n), _dev_ptr(x, "x", n), int(nrhs), info)
     if st != HDSW_ENOCONV or raise_on_noconv:
         _check(st, "hdsw_solve")
     return [(info[i].iters, info[i].rel_residual) for i in range(nrhs)], st
 
 
 def hdsw_apply_precond(ctx, r, z, nrhs):
-    _check(_lib.hdsw_apply_precond(ctx, _dev_ptr(r, "r"), _dev_ptr(z, "z"), int(nrhs)),
+    n = _sizes(ctx)["nglob"] * int(nrhs)
+    _check(_lib.hdsw_apply_precond(ctx, _dev_ptr(r, "r", n), _dev_ptr(z, "z", n), int(nrhs)),
            "hdsw_apply_precond")
 
 
 def hdsw_residual(ctx, b, x, r, nrhs):
     norms = (ctypes.c_double * int(nrhs))()
-    _check(_lib.hdsw_residual(ctx, _dev_ptr(b, "b"), _dev_ptr(x, "x"), _dev_ptr(r, "r"),
-                              int(nrhs), norms), "hdsw_residual")
+    n = _sizes(ctx)["nglob"] * int(nrhs)
+    _check(_lib.hdsw_residual(ctx, _dev_ptr(b, "b", n), _dev_ptr(x, "x", n),
+                              _dev_ptr(r, "r", n), int(nrhs), norms), "hdsw_residual")
     return np.array(norms[:])
 
 
@@ -224,12 +278,14 @@ def hdsw_timing_get(ctx, which):
 
 def hdsw_batch_reserve(ctx, capacity):
     _check(_lib.hdsw_batch_reserve(ctx, int(capacity)), "hdsw_batch_reserve")
+    _sizes(ctx)["cap"] = int(capacity)
 
 
 def hdsw_batch_add(ctx, f, nrhs):
     """f: complex128 GPU tensor [nrhs][interior grid].  Returns the slot ids."""
     slots = (ctypes.c_int * int(nrhs))()
-    _check(_lib.hdsw_batch_add(ctx, _dev_ptr(f, "f"), int(nrhs), slots), "hdsw_batch_add")
+    n = _sizes(ctx)["nint"] * int(nrhs)
+    _check(_lib.hdsw_batch_add(ctx, _dev_ptr(f, "f", n), int(nrhs), slots), "hdsw_batch_add")
     return list(slots[:])
 
 
@@ -239,6 +295,8 @@ def hdsw_batch_step(ctx):
 
 def hdsw_batch_wait(ctx, capacity):
     """Returns the relative residual of every slot (-1 for free slots)."""
+    if int(capacity) < _sizes(ctx)["cap"]:
+        raise ValueError(f"capacity {capacity} is below the reserved {_sizes(ctx)['cap']} slots")
     rel = (ctypes.c_double * int(capacity))()
     _check(_lib.hdsw_batch_wait(ctx, rel), "hdsw_batch_wait")
     return np.array(rel[:])
@@ -256,10 +314,11 @@ def hdsw_batch_ready(ctx):
 def hdsw_batch_take(ctx, slot, x=None):
     """Copies the slot's iterate to x (complex128 GPU tensor, interior grid)
     when given, and frees the slot."""
-    xp = _dev_ptr(x, "x") if x is not None else None
+    xp = _dev_ptr(x, "x", _sizes(ctx)["nint"]) if x is not None else None
     _check(_lib.hdsw_batch_take(ctx, int(slot), xp), "hdsw_batch_take")
 
 
 def hdsw_destroy(ctx):
     if ctx:
         _lib.hdsw_destroy(ctx)
+        _CTX.pop(ctx.value, None)

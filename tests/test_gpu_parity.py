@@ -466,3 +466,69 @@ def test_3d_solve_reaches_global_solution(H, prec):
     e = _rel(x, [u[sl] for u in ug])
     _say(f"  rel err {e:.3e}, iterations {[i for i, _ in info]}")
     assert e < 1e-8
+
+
+def _golden_npz(fname):
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", fname)
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated")
+    return np.load(p)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_3d_ddm_at_the_96cube_block_size(H, prec):
+    # the plane blocks of the 96^3 workload (n_ext = 44: blocks of 1936 nodes,
+    # 44 planes) on a 2 x 2 x 2 partition of a 64^3 grid, W = 6, 8 ppw: one
+    # DDM application (Algorithm 4.1, one round of 8 sweeps) against the
+    # oracle's step-by-step DDM with banded subdomain solves, at 4096 sampled
+    # global nodes and in the global 2-norm (tests/golden/make_3d_samples.py)
+    g = _golden_npz("ddm_c4block.npz")
+    w = wl.make("c3d", N=64, P=2, nrhs=2)
+    prob = O.Problem(w["kappa"], w["h"], w["W"])
+    b = np.stack([O.global_rhs(prob, fi) for fi in w["f"]])
+    _say(f"3d ddm at the 96^3 block size {prec} (64^3, 2x2x2, n = 1936, K = 44)")
+    p = H.HDSW_FP64 if prec == "fp64" else H.HDSW_MIXED
+    c = dict(kap=w["kappa"], h=w["h"], P=w["P"], W=w["W"])
+    ctx = _ctx(H, c, precision=p)
+    try:
+        r = torch.from_numpy(b).cuda()
+        z = torch.zeros_like(r)
+        H.hdsw_apply_precond(ctx, r, z, 2)
+        got = z.cpu().numpy().reshape(2, -1)
+        del r, z
+    finally:
+        H.hdsw_destroy(ctx)
+    samp = got[:, g["index"]]
+    e = max(np.linalg.norm(a - b_) / np.linalg.norm(b_) for a, b_ in zip(samp, g["values"]))
+    en = np.max(np.abs(np.linalg.norm(got, axis=1) - g["norms"]) / g["norms"])
+    _say(f"  sampled rel diff {e:.3e}, norm rel diff {en:.3e}")
+    bar = 1e-10 if prec == "fp64" else 2e-4
+    assert e < bar and en < bar
+
+
+def test_c3d_full_size_against_sampled_global_solution(H):
+    # the 96^3 workload (3 x 3 x 3, W = 6, 8 ppw, 8 RHS) solved as the
+    # benchmark solves it (mixed precision, FP64 refinement to 1e-10), against
+    # the oracle's global solution for its first two sources (the oracle's
+    # DDM-preconditioned FP64 GMRES to 1e-13; tests/golden/make_3d_samples.py)
+    g = _golden_npz("glob_c3d.npz")
+    w = wl.make("c3d")
+    _say("c3d full size mixed")
+    c = dict(kap=w["kappa"], h=w["h"], P=w["P"], W=w["W"])
+    ctx = _ctx(H, c, precision=H.HDSW_MIXED, tol=1e-10, max_iter=40)
+    try:
+        ft = torch.from_numpy(w["f"]).cuda()
+        xt = torch.zeros_like(ft)
+        info, _ = H.hdsw_solve(ctx, ft, xt, ft.shape[0])
+        x = xt.cpu().numpy().reshape(len(w["f"]), -1)
+        del ft, xt
+    finally:
+        H.hdsw_destroy(ctx)
+    nref = len(g["norms"])
+    samp = x[:nref, g["index"]]
+    e = max(np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(samp, g["values"]))
+    en = np.max(np.abs(np.linalg.norm(x[:nref], axis=1) - g["norms"]) / g["norms"])
+    _say(f"  sampled rel err {e:.3e}, norm rel diff {en:.3e}, iterations {[i for i, _ in info]}")
+    assert e < 1e-8
+    assert en < 1e-8

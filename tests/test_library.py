@@ -75,6 +75,25 @@ def test_setup_rejects_invalid_3d_arguments(bad):
     assert ei.value.status == H.HDSW_EINVAL
 
 
+def test_allocator_hooks_default_and_pairing():
+    # no hooks by default; one hook without the other is refused on the host
+    from paper_2003_02585_amd import hdsw as H
+    o = H.hdsw_default_options()
+    assert not o.dev_alloc and not o.dev_free and not o.alloc_ctx
+    alloc = H.DEV_ALLOC_FN(lambda n, c: None)
+    kap = np.full((32, 32), 40.0)
+    with pytest.raises(H.HdswError) as ei:
+        H.hdsw_setup(kap, 1.0 / 32, (2, 2), 8, H.hdsw_default_options(dev_alloc=alloc))
+    assert ei.value.status == H.HDSW_EINVAL
+
+
+def test_binding_refuses_unknown_contexts():
+    import ctypes
+    from paper_2003_02585_amd import hdsw as H
+    with pytest.raises(ValueError):
+        H._sizes(ctypes.c_void_p(12345))
+
+
 def test_setup_rejects_four_dimensions():
     from paper_2003_02585_amd import hdsw as H
     kap = np.full((4, 4, 4, 4), 40.0)
