@@ -162,6 +162,24 @@ hdsw_status hdsw_solve(hdsw_ctx* ctx, const hdsw_c128* f_dev,
 hdsw_status hdsw_apply_precond(hdsw_ctx* ctx, const hdsw_c128* r_dev,
                                hdsw_c128* z_dev, int nrhs);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * DDM application as hdsw_apply_precond, with the same arguments and the
+ * same results bit for bit, that allocates nothing.  Its per-call
+ * workspaces come from a fixed 64 MiB array per device, held by the library
+ * from its first load on that device until the process ends; nrhs is
+ * processed in passes of as many columns as fit (at the 1024^2, 8 x 8
+ * complex64 scale about 3 columns per pass).  Every call on one device
+ * shares that array: calls that overlap on one device (several contexts on
+ * several streams, or threads) race and must be serialized by the caller.
+ * The context's own workspaces are not touched, so it may hold batch slots.
+ * Errors: EINVAL (arguments, pointers as for every entry point),
+ * ENOTFACTORED, ENOMEM (one column's workspace exceeds the 64 MiB array --
+ * a refusal, not an allocation failure), EDEVICE (the array's address could
+ * not be looked up, or a kernel failed). */
+hdsw_status hdsw_apply_precond_noalloc(hdsw_ctx* ctx, const hdsw_c128* r_dev,
+                                       hdsw_c128* z_dev, int nrhs);
+
 /* Global residual r = b - S x on the global grid in FP64 (b on the global
  * grid, both [nrhs][M_z][M_y][M_x] complex128 on the device), and per-RHS
  * norms ||r||_2 written to rnorm_host (nrhs doubles, may be NULL).  r must

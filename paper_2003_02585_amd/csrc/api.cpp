@@ -11,6 +11,7 @@ hdsw_status setup_impl(const hdsw_grid*, const double*, const hdsw_partition*, i
 hdsw_status factor(hdsw_ctx*);
 hdsw_status solve(hdsw_ctx*, const c128*, c128*, int, hdsw_solve_info*);
 hdsw_status apply_precond(hdsw_ctx*, const c128*, c128*, int);
+hdsw_status apply_precond_noalloc(hdsw_ctx*, const c128*, c128*, int);
 hdsw_status residual(hdsw_ctx*, const c128*, const c128*, c128*, int, double*);
 hdsw_status timing_get(hdsw_ctx*, int, double*, long long*, double*, double*);
 hdsw_status batch_reserve(hdsw_ctx*, int);
@@ -89,6 +90,17 @@ hdsw_status hdsw_apply_precond(hdsw_ctx* ctx, const hdsw_c128* r, hdsw_c128* z, 
                                reinterpret_cast<hdsw::c128*>(z), nrhs);
   } catch (const std::bad_alloc&) {
     return HDSW_ENOMEM;
+  } catch (...) {
+    return fail_ctx(ctx);
+  }
+}
+
+hdsw_status hdsw_apply_precond_noalloc(hdsw_ctx* ctx, const hdsw_c128* r, hdsw_c128* z,
+                                       int nrhs) {
+  if (!ctx) return HDSW_EINVAL;
+  try {
+    return hdsw::apply_precond_noalloc(ctx, reinterpret_cast<const hdsw::c128*>(r),
+                                       reinterpret_cast<hdsw::c128*>(z), nrhs);
   } catch (...) {
     return fail_ctx(ctx);
   }

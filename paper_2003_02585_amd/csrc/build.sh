@@ -14,7 +14,7 @@ pids=()
 logs=()
 tmp="$(mktemp -d)"
 trap 'rm -rf "$tmp"' EXIT
-for src in kernels.hip mfma.hip big.hip driver.cpp krylov.cpp api.cpp; do
+for src in kernels.hip mfma.hip big.hip noalloc.hip driver.cpp krylov.cpp api.cpp; do
   o="${tmp}/${src%.*}.o"
   hipcc "${flags[@]}" -x hip -c "${here}/${src}" -o "$o" 2> "${tmp}/${src}.log" &
   objs+=("$o")

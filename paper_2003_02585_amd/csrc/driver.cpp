@@ -12,6 +12,8 @@
 
 namespace hdsw {
 
+hdsw_status scratch_init(int device);
+
 #define HCHK(expr)                                   \
   do {                                               \
     hipError_t e_ = (expr);                          \
@@ -379,6 +381,10 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
     delete c;
     return HDSW_EDEVICE;
   }
+  // device address of this device's allocation-free workspace array (once
+  // per device, with the device current); a failure here only disables
+  // hdsw_apply_precond_noalloc, which then returns EDEVICE
+  (void)scratch_init(c->device);
   c->kappa.assign(kappa, kappa + nint);
 
   GeoDev& d = c->gd;

@@ -24,7 +24,7 @@ KT_SOLVE, KT_GEMM, KT_FACTOR, KT_RESID = range(4)
 
 EXPORTED = [
     "hdsw_default_options", "hdsw_setup", "hdsw_factor", "hdsw_solve",
-    "hdsw_apply_precond", "hdsw_residual", "hdsw_query", "hdsw_timing_enable",
+    "hdsw_apply_precond", "hdsw_apply_precond_noalloc", "hdsw_residual", "hdsw_query", "hdsw_timing_enable",
     "hdsw_timing_get", "hdsw_destroy", "hdsw_status_str", "hdsw_batch_reserve",
     "hdsw_batch_add", "hdsw_batch_step", "hdsw_batch_wait", "hdsw_batch_ready", "hdsw_batch_take",
 ]
@@ -90,6 +90,8 @@ def load_library(path=LIB_PATH):
     lib.hdsw_solve.restype = c_int
     lib.hdsw_apply_precond.argtypes = [c_void_p, c_void_p, c_void_p, c_int]
     lib.hdsw_apply_precond.restype = c_int
+    lib.hdsw_apply_precond_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int]
+    lib.hdsw_apply_precond_noalloc.restype = c_int
     lib.hdsw_residual.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                   ctypes.POINTER(ctypes.c_double)]
     lib.hdsw_residual.restype = c_int
@@ -243,6 +245,14 @@ def hdsw_apply_precond(ctx, r, z, nrhs):
     n = _sizes(ctx)["nglob"] * int(nrhs)
     _check(_lib.hdsw_apply_precond(ctx, _dev_ptr(r, "r", n), _dev_ptr(z, "z", n), int(nrhs)),
            "hdsw_apply_precond")
+
+
+def hdsw_apply_precond_noalloc(ctx, r, z, nrhs):
+    """hdsw_apply_precond without any device allocation (workspaces from the
+    library's fixed per-device array; overlapping calls on one device race)."""
+    n = _sizes(ctx)["nglob"] * int(nrhs)
+    _check(_lib.hdsw_apply_precond_noalloc(ctx, _dev_ptr(r, "r", n), _dev_ptr(z, "z", n),
+                                           int(nrhs)), "hdsw_apply_precond_noalloc")
 
 
 def hdsw_residual(ctx, b, x, r, nrhs):
