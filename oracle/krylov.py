@@ -8,7 +8,10 @@ preconditioner for GMRES, stopping on the relative residual).
   on the true residual at every restart.
 
 S is a scipy sparse matrix (or anything with @), M a callable on flat
-vectors.  Both return (x, history of relative residuals).
+vectors.  Both return (x, history of relative residuals); gmres's history
+holds the true residual at every restart, and its optional `info` dict
+receives the total number of Arnoldi steps ("iters") and the residual
+estimate after every step ("estimates").
 """
 
 import numpy as np
@@ -29,12 +32,13 @@ def refine(S, b, M, tol=1e-10, maxit=50):
     return x, hist
 
 
-def gmres(S, b, M, m=20, tol=1e-10, maxit=200):
+def gmres(S, b, M, m=20, tol=1e-10, maxit=200, info=None):
     b = np.asarray(b, dtype=complex).ravel()
     nb = np.linalg.norm(b)
     n = b.size
     x = np.zeros_like(b)
     hist = []
+    est = []
     it = 0
     while True:
         r = b - S @ x
@@ -78,8 +82,12 @@ def gmres(S, b, M, m=20, tol=1e-10, maxit=200):
             g[k] = cs[k] * g[k]
             k_used = k + 1
             it += 1
+            est.append(abs(g[k + 1]) / nb)
             if abs(g[k + 1]) / nb <= tol or it >= maxit:
                 break
         y = np.linalg.solve(np.triu(H[:k_used, :k_used]), g[:k_used])
         x = x + y @ Z[:k_used]
+    if info is not None:
+        info["iters"] = it
+        info["estimates"] = est
     return x, hist

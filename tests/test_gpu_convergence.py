@@ -1,0 +1,73 @@
+"""Second-order convergence of the GPU solve to the analytic radiating
+solution (Sec. 5.1, Table 1's setup: constant medium, k = 50 pi, 4 x 4
+subdomains, a smoothed point source at the centre of the unit square).
+
+The mixed-precision GPU solve (complex64 DDM, FP64 refinement to a relative
+residual of 1e-10) is compared on three meshes with the free-space solution
+of eq. (helm) with the radiation condition for a unit-mass Gaussian source of
+fixed width s, u = -(i/4) exp(-k^2 s^2 / 2) H0^(1)(k r) (the paper's
+L G = -delta convention), in the annulus 0.2 < r < 0.42 away from source and
+layer.  The layer keeps a fixed physical depth (W = N / 24).  The observed
+rate between successive meshes must be at least 1.8 (the paper reports 2.0).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.special
+
+from paper_2003_02585_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_02585_amd import hdsw
+    return hdsw
+
+
+def test_table1_setup_converges_at_second_order(H):
+    k = 50 * np.pi
+    s = 1.0 / 64
+    meshes = (192, 384, 768)
+    errs = []
+    for N in meshes:
+        h = 1.0 / N
+        W = N // 24
+        kap = wl.constant_kappa((N, N), k)
+        f = wl.gaussian_source((N, N), h, (0.5, 0.5), s)[None].astype(np.complex128)
+        _say(f"table 1 setup: N = {N}, W = {W}, 4 x 4, mixed")
+        opt = H.hdsw_default_options(precision=H.HDSW_MIXED, tol=1e-10, max_iter=40)
+        ctx = H.hdsw_setup(kap, h, (4, 4), W, opt,
+                           stream=torch.cuda.current_stream().cuda_stream)
+        try:
+            H.hdsw_factor(ctx)
+            ft = torch.from_numpy(f).cuda()
+            xt = torch.zeros_like(ft)
+            info, _ = H.hdsw_solve(ctx, ft, xt, 1)
+            u = xt.cpu().numpy()[0]
+        finally:
+            H.hdsw_destroy(ctx)
+        x = (np.arange(N) + 0.5) * h
+        X, Y = np.meshgrid(x, x)
+        r = np.hypot(X - 0.5, Y - 0.5)
+        mask = (r > 0.2) & (r < 0.42)
+        ref = -0.25j * np.exp(-0.5 * (k * s) ** 2) * scipy.special.hankel1(0, k * r)
+        e = np.linalg.norm((u - ref)[mask]) / np.linalg.norm(ref[mask])
+        errs.append(e)
+        _say(f"  {info[0][0]} iterations, residual {info[0][1]:.1e}, rel L2 error {e:.3e}")
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    _say(f"  rates {rates}")
+    assert np.all(rates >= 1.8), (errs, rates)
+    assert errs[-1] < 0.1
