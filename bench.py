@@ -56,6 +56,12 @@ def parse():
     ap.add_argument("--gmres-m", type=int, default=0, help="GMRES(m) instead of refinement")
     ap.add_argument("--rounds", type=int, default=None, help="rounds of sweeps per DDM")
     ap.add_argument("--hbm-budget-gb", type=float, default=0.0)
+    ap.add_argument("--tuned", type=int, default=1,
+                    help="1: launch parameters from the autotuner's cache (tuning.json)")
+    ap.add_argument("--graphs", type=int, default=1,
+                    help="1: DDM applications captured as HIP graphs and replayed; 0: eager")
+    ap.add_argument("--size", default=None,
+                    help="scaled variant of the workload, e.g. N=256,P=4,nrhs=1")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 comparison path (factors too large for both)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -67,6 +73,7 @@ def run_path(H, torch, w, precision, steps, warmup, tol, timing, a):
     stream = torch.cuda.current_stream().cuda_stream
     opt = H.hdsw_default_options(precision=precision, tol=tol, rounds=w["rounds"],
                                  max_iter=40, dedup=a.dedup, gmres_m=a.gmres_m,
+                                 graphs=a.graphs,
                                  hbm_budget=int(a.hbm_budget_gb * (1 << 30)))
     ctx = H.hdsw_setup(w["kappa"], w["h"], w["P"], w["W"], opt, stream=stream)
     try:
@@ -78,6 +85,12 @@ def run_path(H, torch, w, precision, steps, warmup, tol, timing, a):
         t_factor = time.perf_counter() - t0
         kt_factor = H.hdsw_timing_get(ctx, 2)
         H.hdsw_timing_enable(ctx, False)
+        # launch parameters from the autotuner's cache for this shape, if any
+        from paper_2003_02585_amd import autotune
+        _, nops0, _ = H.hdsw_query(ctx)
+        tkey = autotune.shape_key(w["kappa"].shape, w["P"], w["W"],
+                                  precision == H.HDSW_MIXED, w["rounds"], nops0)
+        tuned = autotune.apply_cached(H, ctx, tkey) if a.tuned else None
         f = torch.from_numpy(w["f"]).cuda()
         x = torch.zeros_like(f)
         nrhs = f.shape[0]
@@ -113,11 +126,29 @@ def run_path(H, torch, w, precision, steps, warmup, tol, timing, a):
         torch.cuda.synchronize()
         total = time.perf_counter() - t_all
         kt = None
+        lat_g, total_g = None, None
         if timing:
             kt = {k: H.hdsw_timing_get(ctx, k) for k in range(4)}
             H.hdsw_timing_enable(ctx, False)
+            if a.graphs:
+                # the same solves with kernel events off, so the DDM
+                # applications run as captured graphs (events cannot time a
+                # graph's launches): a second timed region
+                for _ in range(2):
+                    H.hdsw_solve(ctx, f, x, nrhs)
+                lat_g = []
+                torch.cuda.synchronize()
+                t_g = time.perf_counter()
+                for _ in range(steps):
+                    t0 = time.perf_counter()
+                    H.hdsw_solve(ctx, f, x, nrhs)
+                    torch.cuda.synchronize()
+                    lat_g.append(time.perf_counter() - t0)
+                total_g = time.perf_counter() - t_g
         fb, nops, ws = H.hdsw_query(ctx)
-        return dict(total=total, lat=lat, info=info, x=x.cpu().numpy(), t_factor=t_factor,
+        return dict(tuning=dict(key=tkey, params=tuned["params"] if tuned else "built-in rules"),
+                    total=total, lat=lat, info=info, x=x.cpu().numpy(), t_factor=t_factor,
+                    lat_g=lat_g, total_g=total_g,
                     kt=kt, kt_all=kt_all, t_all_solve=t_all_solve, dom=dom,
                     factor_bytes=fb, nops=nops, ws=ws, nrhs=nrhs, kt_factor=kt_factor)
     finally:
@@ -287,13 +318,20 @@ def main():
     # process touches the GPU)
     cpu_raw = None
     if not a.no_cpu_baseline:
+        if a.size:
+            sys.exit("--size runs the GPU paths only: add --no-cpu-baseline")
         cpu_raw = cpu_baseline_run(a.config, a.cpu_workers or min(16, os.cpu_count() or 1),
                                    a.rounds)
     import torch
     from paper_2003_02585_amd import hdsw as H
     from paper_2003_02585_amd import workloads as wl
 
-    w = wl.make(a.config)
+    over = {}
+    if a.size:
+        for kv in a.size.split(","):
+            k, v = kv.split("=")
+            over[k.strip()] = int(v)
+    w = wl.make(a.config, **over)
     if a.rounds is not None:
         w["rounds"] = a.rounds
     mixed = run_path(H, torch, w, H.HDSW_MIXED, a.steps, a.warmup, a.tol, True, a)
@@ -312,7 +350,7 @@ def main():
     # by tests/golden/make_samples.py (oracle only), when present
     err_glob = None
     gpath = os.path.join(ROOT, "tests", "golden", f"samples_{a.config}.npz")
-    if os.path.exists(gpath) and a.rounds is None:
+    if os.path.exists(gpath) and a.rounds is None and not over:
         g = np.load(gpath)
         xs = mixed["x"].reshape(nrhs, -1)[:, g["index"]]
         nref = min(nrhs, len(g["norms"]))
@@ -359,9 +397,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(a, w, nrhs), "nrhs": nrhs, "tol": a.tol,
                    "rounds": w["rounds"], "dedup": a.dedup, "gmres_m": a.gmres_m,
+                   "graphs": a.graphs, "tuning": mixed["tuning"],
                    "distinct_operators": mixed["nops"]},
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "graph_replay": (None if mixed["lat_g"] is None else {
+            "value": round(nrhs * a.steps / mixed["total_g"], 3),
+            "p50_ms": round(float(np.percentile(np.array(mixed["lat_g"]) * 1e3, 50)), 3),
+            "p99_ms": round(float(np.percentile(np.array(mixed["lat_g"]) * 1e3, 99)), 3),
+            "note": "same solves, kernel events off, DDM applications replayed as HIP graphs"}),
         "fp64_value": round(v64, 3) if v64 else None,
         "speedup_mixed_vs_fp64": round(value / v64, 3) if v64 else None,
         "iters_mixed": [i for i, _ in mixed["info"]],

@@ -87,6 +87,10 @@ typedef struct {
   int gmres_m;    /* 0: iterative refinement x += M^{-1}(b - S x);
                      m > 0: right-preconditioned GMRES(m), FP64 Arnoldi     */
   int dedup;      /* share factors between identical subdomain operators    */
+  int graphs;     /* 1: a DDM application applied twice with the same
+                     arrays and column count is captured as a HIP graph and
+                     replayed from then on (same kernels, same results bit
+                     for bit); 0: every launch is issued eagerly             */
   size_t hbm_budget; /* bytes for factors plus workspaces; 0 = no limit      */
   /* Device allocator hooks (both or neither; NULL = hipMalloc / hipFree).
    * Every device allocation of the context -- factors, interface responses,
@@ -108,8 +112,8 @@ typedef struct {
 } hdsw_solve_info;
 
 /* Fills *opt with the defaults: HDSW_MIXED, rounds 1, pml_R 1e-16,
- * tol 1e-10, max_iter 30, gmres_m 0, dedup 1, no budget, no allocator
- * hooks. */
+ * tol 1e-10, max_iter 30, gmres_m 0, dedup 1, graphs 1, no budget, no
+ * allocator hooks. */
 void hdsw_default_options(hdsw_options* opt);
 
 /* Validates the problem, builds the partition, the per-subdomain layer
@@ -234,6 +238,34 @@ hdsw_status hdsw_batch_step(hdsw_ctx* ctx);
 hdsw_status hdsw_batch_wait(hdsw_ctx* ctx, double* rel_residual);
 hdsw_status hdsw_batch_ready(hdsw_ctx* ctx);
 hdsw_status hdsw_batch_take(hdsw_ctx* ctx, int slot, hdsw_c128* x_dev);
+
+/* Launch parameters of the kernels (the autotuner's search space; not a
+ * passage of the paper: they choose how the method's block solves and sweep
+ * steps are laid out on the GPU, never what they compute).  0 in a field
+ * selects the library's built-in rule.
+ *   solve_ng    : complex64 2D block solve, 1 = 8 or 2 = 16 right-hand sides
+ *                 per workgroup (the columns of a product are independent:
+ *                 results do not change).
+ *   sweep_rw    : 2D sweep step, 2 or 4 row tiles of 16 per workgroup (sets
+ *                 how a sum is split in parts, so results change at the
+ *                 rounding level; fixed per context, never per call).
+ *   sweep_kb    : 2D sweep step, 4-deep slices of the interface response
+ *                 per register batch: 6, 8 or 10 (complex64), 3, 4, 5
+ *                 or 6 (complex128); results do not change.
+ *   gemm_skinny : 3D products with at most 8 columns per operator, 1 =
+ *                 stream the matrix through the skinny kernel, 2 = tiled
+ *                 kernel (order of the sum differs at the rounding level).
+ * hdsw_tuning_set validates every field (EINVAL for values outside the
+ * lists above) and drops captured graphs; hdsw_tuning_get returns the
+ * fields as set. */
+typedef struct {
+  int solve_ng;
+  int sweep_rw;
+  int sweep_kb;
+  int gemm_skinny;
+} hdsw_tuning;
+hdsw_status hdsw_tuning_set(hdsw_ctx* ctx, const hdsw_tuning* t);
+hdsw_status hdsw_tuning_get(const hdsw_ctx* ctx, hdsw_tuning* t);
 
 void hdsw_destroy(hdsw_ctx* ctx);
 const char* hdsw_status_str(hdsw_status s);

@@ -20,6 +20,7 @@ hdsw_status batch_step(hdsw_ctx*);
 hdsw_status batch_wait(hdsw_ctx*, double*);
 hdsw_status batch_ready(hdsw_ctx*);
 hdsw_status batch_take(hdsw_ctx*, int, c128*);
+hdsw_status tuning_set(hdsw_ctx*, const TuneParams&);
 void destroy(hdsw_ctx*);
 }  // namespace hdsw
 
@@ -34,6 +35,7 @@ void hdsw_default_options(hdsw_options* o) {
   o->max_iter = 30;
   o->gmres_m = 0;
   o->dedup = 1;
+  o->graphs = 1;
   o->hbm_budget = 0;
   o->dev_alloc = nullptr;
   o->dev_free = nullptr;
@@ -194,6 +196,29 @@ hdsw_status hdsw_batch_take(hdsw_ctx* ctx, int slot, hdsw_c128* x) {
   } catch (...) {
     return fail_ctx(ctx);
   }
+}
+
+hdsw_status hdsw_tuning_set(hdsw_ctx* ctx, const hdsw_tuning* t) {
+  if (!ctx || !t) return HDSW_EINVAL;
+  hdsw::TuneParams p;
+  p.solve_ng = t->solve_ng;
+  p.sweep_rw = t->sweep_rw;
+  p.sweep_kb = t->sweep_kb;
+  p.gemm_skinny = t->gemm_skinny;
+  try {
+    return hdsw::tuning_set(ctx, p);
+  } catch (...) {
+    return fail_ctx(ctx);
+  }
+}
+
+hdsw_status hdsw_tuning_get(const hdsw_ctx* ctx, hdsw_tuning* t) {
+  if (!ctx || !t) return HDSW_EINVAL;
+  t->solve_ng = ctx->tune.solve_ng;
+  t->sweep_rw = ctx->tune.sweep_rw;
+  t->sweep_kb = ctx->tune.sweep_kb;
+  t->gemm_skinny = ctx->tune.gemm_skinny;
+  return HDSW_OK;
 }
 
 void hdsw_destroy(hdsw_ctx* ctx) { hdsw::destroy(ctx); }

@@ -355,7 +355,7 @@ hipError_t gemm(hipStream_t st, const GemmArgs& a_in, int maxcols, int ngroups) 
   constexpr int BK = sizeof(T) == 4 ? 32 : 16;
   const int nrt = (a.M + GM - 1) / GM, nct = (maxcols + GN - 1) / GN;
   // at most 8 columns per group: the product streams A (HBM-bound)
-  if (maxcols <= 8 && a.ksplit == 1 && (!a.a_rt || BK == 32)) {
+  if (maxcols <= 8 && a.ksplit == 1 && !a.no_skinny && (!a.a_rt || BK == 32)) {
     dim3 g2(8 * ((nrt + 7) / 8), ngroups, 1);
     if (a.a_rt) {
       if (a.M % GM != 0) return hipErrorInvalidValue;
@@ -737,6 +737,7 @@ hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int
         --ks;
       a.ksplit = ks;
       a.part = c->d_gpart;
+      a.no_skinny = c->tune.gemm_skinny == 2;
       e = gemm<T>(c->stream, a, maxcnt * C, ngroups);
       if (e != hipSuccess) return e;
     }

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <new>
 #include <unordered_map>
@@ -285,6 +286,8 @@ static void resolve_timing(hdsw_ctx* c) {
       c->tm.launches[e.cls] += 1;
       c->tm.flops[e.cls] += e.flops;
       c->tm.bytes[e.cls] += e.bytes;
+    } else {
+      (void)hipGetLastError();   // a failed read must not reach the next launch check
     }
   }
   p.pending.clear();
@@ -735,10 +738,13 @@ hdsw_status factor(hdsw_ctx* c) {
 }
 
 // ------------------------------------------------------------ workspaces
+static void graphs_clear(hdsw_ctx* c);
+
 static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   const Geometry& g = c->g;
   size_t e = elt(c);
   if (C > c->Cmax) {
+    graphs_clear(c);   // captured applications hold the old workspace addresses
     void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_srcsum, c->d_y, c->d_out, c->d_gpart,
                     c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
     for (void* p : ptrs) dev_free(c, p);
@@ -781,6 +787,7 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   // the Krylov basis is sized for the workspaces' column count: regrow it
   // whenever the workspaces grew since it was allocated
   if (need_gmres && (c->gm_m != c->opt.gmres_m || !c->d_V || c->gm_cols < c->Cmax)) {
+    graphs_clear(c);
     dev_free(c, c->d_V);
     dev_free(c, c->d_Z);
     dev_free(c, c->d_dots);
@@ -850,13 +857,66 @@ static hdsw_status ddm_impl(hdsw_ctx* c, const c128* r, c128* out, int C, int ac
   return HDSW_OK;
 }
 
-static hdsw_status ddm(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
+static hdsw_status ddm_eager(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
   return c->opt.precision == HDSW_MIXED ? ddm_impl<float>(c, r, out, C, accumulate)
                                         : ddm_impl<double>(c, r, out, C, accumulate);
 }
 
+static void graphs_clear(hdsw_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->graph_seen.clear();
+}
+
+// One DDM application, from a captured graph when the same (input, output,
+// columns, accumulate) was applied before.  The launch sequence has no host
+// synchronization and clears its buffers with fill kernels (no memset
+// nodes), so it is recorded on a private stream and replayed on the
+// context's stream; the replay runs the same kernels with the same
+// arguments, so results equal the eager launches bit for bit.  With kernel
+// timing on, launches are eager: HIP events recorded by a graph's event
+// nodes cannot be read as elapsed times.
+static hdsw_status ddm(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
+  if (!c->opt.graphs || c->tm.mask) return ddm_eager(c, r, out, C, accumulate);
+  const hdsw_ctx::GraphKey key{r, out, C, accumulate};
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (!c->graph_seen.count(key)) {
+      if (c->graph_seen.size() >= 256) c->graph_seen.clear();
+      c->graph_seen.insert(key);
+      return ddm_eager(c, r, out, C, accumulate);
+    }
+    if (c->graphs.size() >= 64) graphs_clear(c);
+    if (!c->cap_stream) HCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t s = c->stream;
+    c->stream = c->cap_stream;
+    hdsw_status st = ddm_eager(c, r, out, C, accumulate);
+    c->stream = s;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (st == HDSW_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != HDSW_OK) {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      return st;
+    }
+    HCHK(e);
+    it = c->graphs.emplace(key, exec).first;
+  }
+  HCHK(hipGraphLaunch(it->second, c->stream));
+  return HDSW_OK;
+}
+
 hdsw_status ddm_dispatch(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
   return ddm(c, r, out, C, accumulate);
+}
+
+// Eager form for callers that swap the context's workspaces for a call
+// (captured graphs hold the context's own workspace addresses).
+hdsw_status ddm_dispatch_eager(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
+  return ddm_eager(c, r, out, C, accumulate);
 }
 
 static size_t max_cols(hdsw_ctx* c) {
@@ -1153,8 +1213,27 @@ hdsw_status timing_get(hdsw_ctx* c, int which, double* ms, long long* n, double*
   return HDSW_OK;
 }
 
+hdsw_status tuning_set(hdsw_ctx* c, const TuneParams& t) {
+  if (c->sticky != HDSW_OK) return c->sticky;
+  const bool c64 = c->opt.precision == HDSW_MIXED;
+  auto in = [](int v, std::initializer_list<int> ok) {
+    for (int o : ok)
+      if (v == o) return true;
+    return false;
+  };
+  if (!in(t.solve_ng, {0, 1, 2}) || !in(t.sweep_rw, {0, 2, 4}) ||
+      !(c64 ? in(t.sweep_kb, {0, 6, 8, 10}) : in(t.sweep_kb, {0, 3, 4, 5, 6})) ||
+      !in(t.gemm_skinny, {0, 1, 2}))
+    return HDSW_EINVAL;
+  graphs_clear(c);   // captured launches hold the old parameters
+  c->tune = t;
+  return HDSW_OK;
+}
+
 void destroy(hdsw_ctx* c) {
   if (!c) return;
+  graphs_clear(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->h_norm) (void)hipHostFree(c->h_norm);
   if (c->step_done) (void)hipEventDestroy(c->step_done);
   resolve_timing(c);

@@ -6,7 +6,10 @@
 
 #include <array>
 #include <cstdint>
+#include <map>
+#include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hdsw.h"
@@ -157,6 +160,15 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Launch parameters of the autotuner's search space (0: built-in rule).
+struct TuneParams {
+  int solve_ng = 0;     // 2D complex64 block solve: 1 = 8, 2 = 16 columns per workgroup
+  int sweep_rw = 0;     // 2D sweep step: 2 or 4 row tiles per workgroup
+  int sweep_kb = 0;     // 2D sweep step: slices of T per register batch
+                        // (complex64 6/8/10, complex128 3/4/5/6)
+  int gemm_skinny = 0;  // 3D products with <= 8 columns: 1 streaming, 2 tiled
+};
+
 struct Timing {
   int mask = 0;                     // bit k: time kernel class k
   double ms[4] = {0, 0, 0, 0};
@@ -252,6 +264,7 @@ struct hdsw_ctx {
   hdsw::c128* d_Z = nullptr;        // [m][C][glob]
   hdsw::c128* d_dots = nullptr;     // [m+1][C]
   hdsw::Timing tm;
+  hdsw::TuneParams tune;
 
   // continuous batching: occupied column slots, compacted to 0..nact-1
   int batch_cap = 0;
@@ -262,6 +275,15 @@ struct hdsw_ctx {
   double* h_norm = nullptr;         // pinned host copy of the step's norms
   hipEvent_t step_done = nullptr;
   int step_cols = 0;                // columns the in-flight step covers
+
+  // captured DDM applications: (input, output, columns, accumulate) ->
+  // executable graph; a key is captured the second time it is applied and
+  // replayed from then on.  Cleared whenever the workspaces or the launch
+  // parameters change.
+  using GraphKey = std::tuple<const void*, const void*, int, int>;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::set<GraphKey> graph_seen;
+  hipStream_t cap_stream = nullptr;    // private stream the captures record on
 };
 
 namespace hdsw {
@@ -298,6 +320,9 @@ struct GemmArgs {
   int ksplit;
   void* part;
   int part_cols;
+  // 1: products with at most 8 columns use the tiled kernel too (the
+  // autotuner's choice); 0: they stream A through the skinny kernel
+  int no_skinny;
 };
 
 template <class T>

@@ -486,11 +486,14 @@ hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) 
   }
   // complex64: 16 columns per workgroup once 8-column workgroups would take
   // more than two rounds of the 256 CUs (throughput-bound: every X tile then
-  // feeds twice the MFMAs); 8 while the chain latency dominates.  complex128
-  // keeps 8 (16 would not fit the register file)
+  // feeds twice the MFMAs); 8 while the chain latency dominates, unless the
+  // autotuner chose (solve_ng; columns of an MFMA product are independent,
+  // so the choice does not change results).  complex128 keeps 8 (16 would
+  // not fit the register file)
   if constexpr (sizeof(T) == 4) {
     const long long wg8 = (long long)((C + 7) / 8) * nbatch * 2;
-    if (C >= 16 && wg8 > 2 * 256 && solve_nw<T>(c->g.nP, 2) == 8)
+    const bool wide = c->tune.solve_ng ? c->tune.solve_ng == 2 : (C >= 16 && wg8 > 2 * 256);
+    if (wide && C > 8 && solve_nw<T>(c->g.nP, 2) == 8)
       return launch_solve_nw<T, 8, 2>(c, nbatch, d_ops, C);
   }
   const int nw = solve_nw<T>(c->g.nP, 1);
@@ -1390,6 +1393,7 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
       if (e != hipSuccess) return e;
     } else {
       if (tk != gemm_bk<T>()) return hipErrorInvalidValue;
+      a.no_skinny = c->tune.gemm_skinny == 2;
       hipError_t e = gemm<T>(c->stream, a, c->sg_maxcnt[sidx] * C, c->sg_n[sidx]);
       if (e != hipSuccess) return e;
     }
@@ -1408,11 +1412,13 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
   const int lcap = sweep_lcap<T>();
   const int nsub_chunks = std::max(1, (flen + lcap - 1) / lcap);
   const int LMAX = std::max(4, ((flen + nsub_chunks - 1) / nsub_chunks + 3) / 4 * 4);
-  // 4-deep slices of T per register batch (two batches in flight): a wave's
-  // 20 (complex64) or 10 (complex128) slices of a 1024^2 face chunk in two
-  // batches (measured: complex64 8 -> 10 shortens the step by 5%, 12 is
-  // slower again; complex128 4 -> 5 by 4%)
-  constexpr int KB = sizeof(T) == 4 ? 10 : 5;
+  // 4-deep slices of T per register batch (two batches in flight): by
+  // default a wave's 20 (complex64) or 10 (complex128) slices of a 1024^2
+  // face chunk in two batches (measured: complex64 8 -> 10 shortens the step
+  // by 5%, 12 is slower again; complex128 4 -> 5 by 4%); the autotuner may
+  // choose another compiled depth (sweep_kb).  The depth does not change
+  // the order of the sum.
+  const int kb_sel = c->tune.sweep_kb ? c->tune.sweep_kb : (sizeof(T) == 4 ? 10 : 5);
   // the step's subdomains in launches of at most kStepListMax
   for (int b0 = 0; b0 < cnt; b0 += kStepListMax) {
     StepList sl{};
@@ -1429,8 +1435,9 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
     // two-tile workgroups fits in kSweepRows workgroups, four on larger
     // steps (measured: two tiles best at 1024^2 with 16 RHS, four on the
     // large steps at 2048^2 with 64 RHS)
-    auto launch = [&](auto rw) -> hipError_t {
+    auto launch_kb = [&](auto rw, auto kbc) -> hipError_t {
       constexpr int RW = decltype(rw)::value;
+      constexpr int KB = decltype(kbc)::value;
       const int nrt = (nout + 16 * RW - 1) / (16 * RW);
       // LDS: the staged operand pairs, or the KH partial tiles of the sum
       size_t lds = std::max<size_t>((size_t)2 * LMAX * kSweepRS,
@@ -1442,9 +1449,23 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
                          L == 0 ? 1 : 0, LMAX, nsub_chunks, c->gd);
       return hipGetLastError();
     };
+    auto launch = [&](auto rw) -> hipError_t {
+      if constexpr (sizeof(T) == 4) {
+        if (kb_sel == 6) return launch_kb(rw, std::integral_constant<int, 6>{});
+        if (kb_sel == 8) return launch_kb(rw, std::integral_constant<int, 8>{});
+        if (kb_sel == 10) return launch_kb(rw, std::integral_constant<int, 10>{});
+      } else {
+        if (kb_sel == 3) return launch_kb(rw, std::integral_constant<int, 3>{});
+        if (kb_sel == 4) return launch_kb(rw, std::integral_constant<int, 4>{});
+        if (kb_sel == 5) return launch_kb(rw, std::integral_constant<int, 5>{});
+        if (kb_sel == 6) return launch_kb(rw, std::integral_constant<int, 6>{});
+      }
+      return hipErrorInvalidValue;   // not a compiled depth (checked when set)
+    };
     const long long wg2 = 8LL * (((nout + 31) / 32 + 7) / 8) * sl.n;
-    hipError_t e = wg2 > kSweepRows ? launch(std::integral_constant<int, 4>{})
-                                    : launch(std::integral_constant<int, 2>{});
+    const int rw_sel = c->tune.sweep_rw ? c->tune.sweep_rw : (wg2 > kSweepRows ? 4 : 2);
+    hipError_t e = rw_sel == 4 ? launch(std::integral_constant<int, 4>{})
+                               : launch(std::integral_constant<int, 2>{});
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -21,7 +21,7 @@
 
 namespace hdsw {
 
-hdsw_status ddm_dispatch(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate);
+hdsw_status ddm_dispatch_eager(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate);
 hdsw_status check_dev_ptr(const hdsw_ctx* c, const void* p, size_t bytes);
 
 constexpr size_t kScratchBytes = size_t(64) << 20;
@@ -117,8 +117,8 @@ hdsw_status apply_precond_noalloc(hdsw_ctx* c, const c128* r, c128* z, int nrhs)
     c->d_out = c->g.dim == 3 ? b + k.out : nullptr;
     c->d_gpart = c->g.dim == 3 ? b + k.gpart : nullptr;
     c->gpart_bytes = k.gpart_bytes;
-    st = ddm_dispatch(c, r + (size_t)c0 * c->g.glob_nodes, z + (size_t)c0 * c->g.glob_nodes,
-                      C, 0);
+    st = ddm_dispatch_eager(c, r + (size_t)c0 * c->g.glob_nodes,
+                            z + (size_t)c0 * c->g.glob_nodes, C, 0);
   }
   c->d_panel = saved[0];
   c->d_slots = saved[1];

@@ -27,6 +27,7 @@ EXPORTED = [
     "hdsw_apply_precond", "hdsw_apply_precond_noalloc", "hdsw_residual", "hdsw_query", "hdsw_timing_enable",
     "hdsw_timing_get", "hdsw_destroy", "hdsw_status_str", "hdsw_batch_reserve",
     "hdsw_batch_add", "hdsw_batch_step", "hdsw_batch_wait", "hdsw_batch_ready", "hdsw_batch_take",
+    "hdsw_tuning_set", "hdsw_tuning_get",
 ]
 
 
@@ -46,9 +47,15 @@ class hdsw_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("rounds", ctypes.c_int),
                 ("pml_R", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("gmres_m", ctypes.c_int),
-                ("dedup", ctypes.c_int), ("hbm_budget", ctypes.c_size_t),
+                ("dedup", ctypes.c_int), ("graphs", ctypes.c_int),
+                ("hbm_budget", ctypes.c_size_t),
                 ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p)]
+
+
+class hdsw_tuning(ctypes.Structure):
+    _fields_ = [("solve_ng", ctypes.c_int), ("sweep_rw", ctypes.c_int),
+                ("sweep_kb", ctypes.c_int), ("gemm_skinny", ctypes.c_int)]
 
 
 class hdsw_solve_info(ctypes.Structure):
@@ -117,6 +124,10 @@ def load_library(path=LIB_PATH):
     lib.hdsw_batch_ready.restype = c_int
     lib.hdsw_batch_take.argtypes = [c_void_p, c_int, c_void_p]
     lib.hdsw_batch_take.restype = c_int
+    lib.hdsw_tuning_set.argtypes = [c_void_p, ctypes.POINTER(hdsw_tuning)]
+    lib.hdsw_tuning_set.restype = c_int
+    lib.hdsw_tuning_get.argtypes = [c_void_p, ctypes.POINTER(hdsw_tuning)]
+    lib.hdsw_tuning_get.restype = c_int
     lib.hdsw_destroy.argtypes = [c_void_p]
     lib.hdsw_destroy.restype = None
     lib.hdsw_status_str.argtypes = [c_int]
@@ -326,6 +337,26 @@ def hdsw_batch_take(ctx, slot, x=None):
     when given, and frees the slot."""
     xp = _dev_ptr(x, "x", _sizes(ctx)["nint"]) if x is not None else None
     _check(_lib.hdsw_batch_take(ctx, int(slot), xp), "hdsw_batch_take")
+
+
+TUNING_FIELDS = ("solve_ng", "sweep_rw", "sweep_kb", "gemm_skinny")
+
+
+def hdsw_tuning_set(ctx, **fields):
+    """Sets the kernels' launch parameters (0 = built-in rule); unknown
+    fields raise TypeError, values outside the compiled lists HdswError."""
+    t = hdsw_tuning()
+    for k, v in fields.items():
+        if k not in TUNING_FIELDS:
+            raise TypeError(f"unknown tuning field {k}")
+        setattr(t, k, int(v))
+    _check(_lib.hdsw_tuning_set(ctx, ctypes.byref(t)), "hdsw_tuning_set")
+
+
+def hdsw_tuning_get(ctx):
+    t = hdsw_tuning()
+    _check(_lib.hdsw_tuning_get(ctx, ctypes.byref(t)), "hdsw_tuning_get")
+    return {k: getattr(t, k) for k in TUNING_FIELDS}
 
 
 def hdsw_destroy(ctx):

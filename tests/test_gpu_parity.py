@@ -169,6 +169,30 @@ def test_solve_reaches_global_solution(H, prec, N, W, P, layer, rounds, gm):
     assert all(r <= 1e-11 for _, r in info)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_one_round_gmres_two_layer(H, prec):
+    # one round of sweeps as the preconditioner on the two-layer medium (the
+    # paper's setting in Sec. 5.2) needs a long Krylov space here: GMRES(60)
+    # without restarts within 60 steps, as in the oracle's pin at this size
+    c = _case(256, 16, (8, 8), 1.5, nrhs=3, seed=43)
+    ug = O.solve_global(c["prob"], c["b"])
+    sl = c["prob"].interior_slice()
+    _say(f"one-round GMRES(60) two-layer 256^2 8x8 {prec}")
+    p = H.HDSW_FP64 if prec == "fp64" else H.HDSW_MIXED
+    ctx = _ctx(H, c, precision=p, rounds=1, gmres_m=60, tol=1e-11, max_iter=60)
+    try:
+        ft = torch.from_numpy(c["f"]).cuda()
+        xt = torch.zeros_like(ft)
+        info, _ = H.hdsw_solve(ctx, ft, xt, 3)
+        x = xt.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    e = _rel(x, [u[sl] for u in ug])
+    _say(f"  rel err {e:.3e}, iterations {[i for i, _ in info]}")
+    assert e < 1e-8
+    assert all(r <= 1e-11 for _, r in info)
+
+
 def test_residual_matches_oracle_operator(H):
     c = _case(40, 6, (2, 2), 1.5, nrhs=2)
     S = O.global_operator(c["prob"])

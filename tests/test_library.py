@@ -35,7 +35,7 @@ def test_status_strings_and_defaults():
     for s in range(7):
         assert H.hdsw_status_str(s).startswith("HDSW")
     o = H.hdsw_default_options()
-    assert (o.precision, o.rounds, o.gmres_m, o.dedup) == (H.HDSW_MIXED, 1, 0, 1)
+    assert (o.precision, o.rounds, o.gmres_m, o.dedup, o.graphs) == (H.HDSW_MIXED, 1, 0, 1, 1)
     assert o.pml_R == 1e-16 and o.tol == 1e-10
 
 
