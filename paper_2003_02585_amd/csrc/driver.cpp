@@ -866,6 +866,7 @@ static void graphs_clear(hdsw_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   c->graph_seen.clear();
+  c->graph_bad.clear();
 }
 
 // One DDM application, from a captured graph when the same (input, output,
@@ -879,6 +880,7 @@ static void graphs_clear(hdsw_ctx* c) {
 static hdsw_status ddm(hdsw_ctx* c, const c128* r, c128* out, int C, int accumulate) {
   if (!c->opt.graphs || c->tm.mask) return ddm_eager(c, r, out, C, accumulate);
   const hdsw_ctx::GraphKey key{r, out, C, accumulate};
+  if (c->graph_bad.count(key)) return ddm_eager(c, r, out, C, accumulate);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     if (!c->graph_seen.count(key)) {
@@ -888,7 +890,20 @@ static hdsw_status ddm(hdsw_ctx* c, const c128* r, c128* out, int C, int accumul
     }
     if (c->graphs.size() >= 64) graphs_clear(c);
     if (!c->cap_stream) HCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    HCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    // A capture can be refused or invalidated by the runtime (for example
+    // by another thread's work on the legacy default stream).  Nothing
+    // recorded ran, so the application then runs eagerly and the key stays
+    // eager; errors seen while recording are not device errors.
+    const hdsw_status sticky0 = c->sticky;
+    auto give_up = [&]() {
+      (void)hipGetLastError();
+      c->sticky = sticky0;
+      if (c->graph_bad.size() >= 256) c->graph_bad.clear();
+      c->graph_bad.insert(key);
+      return ddm_eager(c, r, out, C, accumulate);
+    };
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return give_up();
     hipStream_t s = c->stream;
     c->stream = c->cap_stream;
     hdsw_status st = ddm_eager(c, r, out, C, accumulate);
@@ -898,11 +913,10 @@ static hdsw_status ddm(hdsw_ctx* c, const c128* r, c128* out, int C, int accumul
     hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
     if (st == HDSW_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
-    if (st != HDSW_OK) {
+    if (st != HDSW_OK || e != hipSuccess) {
       if (exec) (void)hipGraphExecDestroy(exec);
-      return st;
+      return give_up();
     }
-    HCHK(e);
     it = c->graphs.emplace(key, exec).first;
   }
   HCHK(hipGraphLaunch(it->second, c->stream));

@@ -265,6 +265,7 @@ struct hdsw_ctx {
   hdsw::c128* d_dots = nullptr;     // [m+1][C]
   hdsw::Timing tm;
   hdsw::TuneParams tune;
+  bool factor_mfma = true;          // 2D blocks: blocked inversion on the matrix cores
 
   // continuous batching: occupied column slots, compacted to 0..nact-1
   int batch_cap = 0;
@@ -283,6 +284,7 @@ struct hdsw_ctx {
   using GraphKey = std::tuple<const void*, const void*, int, int>;
   std::map<GraphKey, hipGraphExec_t> graphs;
   std::set<GraphKey> graph_seen;
+  std::set<GraphKey> graph_bad;        // keys whose capture the runtime refused
   hipStream_t cap_stream = nullptr;    // private stream the captures record on
 };
 

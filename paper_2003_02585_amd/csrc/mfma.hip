@@ -838,9 +838,434 @@ __global__ __launch_bounds__(1024) void k_factor_reg(cpx<T>* X, size_t xstride,
     }
 }
 
+// Blocked Gauss-Jordan inversion of a line block on the matrix cores.
+// Block formation and pivot rule as in k_factor_reg (partial pivoting: for
+// column j the largest |re| + |im| among the rows not yet used as a pivot,
+// lowest row on ties; columns in natural order), with three differences:
+//  * rows are never interchanged: the pivot row p(j) of every column is
+//    recorded, and the permutations are applied when the inverse is written
+//    out, X[q(a)][p(b)] = M[a][b] with q the inverse of p;
+//  * the block lives in MFMA accumulator tiles in registers: tile (rt, ct)
+//    holds rows 16 rt.. and complex columns 8 ct.. as 16 real columns
+//    [Re | Im]; 8 waves form a 2 x 4 grid, wave (wr, wc) owning row tiles
+//    wr, wr + 2, .. and column tiles wc, wc + 4, ..;
+//  * columns are eliminated in panels of 16.  A panel's columns are
+//    gathered to LDS and eliminated there by one wave (in-place
+//    Gauss-Jordan restricted to the panel).  The panel column pivoted at
+//    row p_k then holds T e_{p_k}, T the product of the panel's elementary
+//    eliminations; T differs from the identity only in the columns p_k, so
+//    T = I + W S^T with W = (eliminated panel) - (unit vectors e_{p_k}),
+//    and every other column is updated by one rank-16 complex product,
+//      M[:, rest] += W R,   R = rows p_1..p_16 of M[:, rest] before the
+//    update, as two real MFMAs per 4-deep slice with R staged as the pairs
+//    ([Re r | Im r], [-Im r | Re r]).
+// The update order differs from the unblocked kernels, so results agree
+// with them to rounding.
+// The value of the neighbouring lane of a lane pair (lane ^ 1), by a DPP
+// quad permutation (no LDS round trip).
+__device__ __forceinline__ float swap_pair_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_pair_f(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Largest value over the 64 lanes of the wave, returned in every lane:
+// quad permutations and row mirrors reduce each row of 16 lanes, row
+// broadcasts combine the rows into lane 63.
+__device__ __forceinline__ unsigned dpp_max(unsigned v, unsigned t) { return v > t ? v : t; }
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  const int iv = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(iv, iv, 0xB1, 0xF, 0xF, false));
+  int w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x4E, 0xF, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x141, 0xF, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x140, 0xF, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x142, 0xA, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x143, 0xC, 0xF, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// The value of lane l (wave-uniform) of v, into a scalar register.
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <class T>
+__device__ __forceinline__ cpx<T> swap_pair(cpx<T> v) {
+  return mk<T>(swap_pair_f(v.re), swap_pair_f(v.im));
+}
+
+template <class T, int RA, int CB>
+__global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
+                                                     const cpx<T>* coefT, size_t cstride,
+                                                     GeoDev g, int step, int middle, int* flag,
+                                                     int nops, int ld) {
+  typedef typename MF<T>::v4 v4;
+  constexpr int RS = (32 * RA + 63) / 64;        // panel rows per lane of the eliminating wave
+  extern __shared__ unsigned char smem_raw[];
+  const int op = blockIdx.x, half = blockIdx.y;
+  if (op >= nops) return;
+  const int n = g.n, nP = g.nP, K = g.K, mid = g.mid;
+  int k, pa = -1, fa = 0, pb2 = -1, fb = 0;
+  if (middle) {
+    if (half) return;
+    k = mid;
+    pa = mid - 1;
+    fa = mid;
+    pb2 = mid + 1;
+    fb = mid + 1;
+  } else if (half == 0) {
+    k = step;
+    if (k >= mid) return;
+    if (k > 0) { pa = k - 1; fa = k; }
+  } else {
+    k = K - 1 - step;
+    if (k <= mid) return;
+    if (k < K - 1) { pa = k + 1; fa = k + 1; }
+  }
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 1, wc = wave >> 1;        // 2 x 4 grid of waves
+  const int nMt = nP >> 4, nCt = nP >> 3;
+  const int jc = lane & 15, cc = jc & 7, part = jc >> 3;
+  cpx<T>* PJ = reinterpret_cast<cpx<T>*>(smem_raw);   // [16][nP] panel columns
+  T* Wr = reinterpret_cast<T*>(PJ + 16 * nP);         // [16][ld] W, planar
+  T* Wi = Wr + 16 * ld;
+  T* Rr = Wi + 16 * ld;                               // [16][ld] R, planar
+  T* Ri = Rr + 16 * ld;
+  int* pivr = reinterpret_cast<int*>(Ri + 16 * ld);   // [nP] column -> pivot row
+  int* invp = pivr + nP;                              // [nP] row -> column it pivots
+  cpx<T>* rsb = reinterpret_cast<cpx<T>*>(invp + nP + (nP & 1));   // [16] pivot row
+  cpx<T>* candrow = rsb + 16;                         // [2][8][16] offered pivot rows
+  unsigned* candk = reinterpret_cast<unsigned*>(candrow + 2 * 8 * 16);   // [2][8] their keys
+                                                      // (16-byte aligned: offsets are
+                                                      // multiples of 16 bytes)
+  for (int i = tid; i < nP; i += 512) {
+    pivr[i] = i;
+    invp[i] = i < n ? (1 << 20) : i;                  // padding rows keep their place
+  }
+  const cpx<T>* Xo = X + (size_t)op * xstride;
+  // distinct blocks of X: the output block and the neighbours' inverses do
+  // not overlap, so their loads and stores may be reordered
+  cpx<T>* __restrict__ Mout = X + (size_t)op * xstride + (size_t)k * nP * nP;
+  const cpx<T>* co = coefT + (size_t)op * cstride;
+  const cpx<T>* __restrict__ ax = co + (size_t)k * (n + 1);
+  const cpx<T>* __restrict__ ay = co + (size_t)K * (n + 1);
+  const cpx<T>* __restrict__ dg = co + (size_t)K * (n + 1) + (size_t)(K + 1) * n + (size_t)k * n;
+  const cpx<T>* __restrict__ PA = pa >= 0 ? Xo + (size_t)pa * nP * nP : nullptr;
+  const cpx<T>* __restrict__ PB = pb2 >= 0 ? Xo + (size_t)pb2 * nP * nP : nullptr;
+  // D_k = A_k - B X_{k-1} B (- B X_{k+1} B for the middle line), formed
+  // column-major in the output block, then read into the accumulators
+  for (int idx = tid; idx < nP * nP; idx += 512) {
+    const int col = idx / nP, row = idx - col * nP;
+    cpx<T> v = mk<T>(T(0), T(0));
+    if (row < n && col < n) {
+      // the source is chosen as a pointer and read field by field: a struct
+      // copy under a condition would keep v in private memory
+      const cpx<T>* src = row == col ? dg + row : col == row + 1 ? ax + col
+                          : row == col + 1 ? ax + row : nullptr;
+      if (src) v = mk<T>(src->re, src->im);
+      if (PA) v = v - ay[(size_t)fa * n + row] * ay[(size_t)fa * n + col] * PA[idx];
+      if (PB) v = v - ay[(size_t)fb * n + row] * ay[(size_t)fb * n + col] * PB[idx];
+    }
+    Mout[idx] = v;
+  }
+  __threadfence_block();
+  __syncthreads();
+  v4 acc[RA][CB];
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int rt = wr + 2 * a, ct = wc + 4 * b;
+      // unconditional loads (a tile past the block reads entry 0; its
+      // accumulators are never written out)
+      const unsigned base = (rt < nMt && ct < nCt) ? (unsigned)(8 * ct + cc) * nP + 16 * rt : 0u;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const cpx<T> v = Mout[base + MF<T>::row(lane, i)];
+        acc[a][b][i] = part ? v.im : v.re;
+      }
+    }
+  __syncthreads();
+  for (int q = 0; 16 * q < n; ++q) {
+    const int j0 = 16 * q;
+    // the lane index, opaque to the compiler in every iteration: the tiles'
+    // row and column offsets are recomputed per panel instead of being
+    // hoisted out of the loop into registers the accumulators need
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int cq = ln & 7, pq = (ln >> 3) & 1, rq = ln & 15;
+    // a. the panel's tiles to LDS
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int rt = wr + 2 * a, ct = wc + 4 * b;
+        if (rt < nMt && (ct >> 1) == q) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 16 * rt + MF<T>::row(ln, i);
+            T* dst = reinterpret_cast<T*>(PJ + (size_t)(8 * (ct - 2 * q) + cq) * nP + row);
+            dst[pq] = acc[a][b][i];
+          }
+        }
+      }
+    lds_barrier();
+    // c. the panel's columns are eliminated with threads 2 r and 2 r + 1
+    //    holding row r of the panel in registers (8 columns each, r < nP).
+    //    Per pivot, one barrier: every wave finds its best candidate row by
+    //    cross-lane moves (the key: |re| + |im| with its exponent and leading
+    //    15 mantissa bits, then the lowest row) and offers it, key and row,
+    //    in LDS; after the barrier every thread takes the best of the eight
+    //    offers as the pivot row.  Offers alternate between two buffers by
+    //    pivot parity, so a pivot's offers never overwrite ones still read.
+    {
+      const bool has = tid < 2 * nP;
+      const int row = has ? tid >> 1 : 0, h = tid & 1;
+      bool used = !has || row >= n || invp[row] < n;
+      cpx<T> pr[8];
+#pragma unroll
+      for (int c2 = 0; c2 < 8; ++c2) pr[c2] = PJ[(size_t)(8 * h + c2) * nP + row];
+      int mykk = -1;                                // panel column this row pivots
+      const int kend = min(16, n - j0);             // padding columns: no pivot
+#pragma unroll 1
+      for (int kk = 0; kk < kend; ++kk) {
+        const int j = j0 + kk, slot = kk & 1;
+        // column kk of this row, from the thread of the row that holds it
+        // (the neighbouring lane: a DPP swap within lane pairs)
+        cpx<T> own = pr[0];
+#pragma unroll
+        for (int c2 = 1; c2 < 8; ++c2)
+          if ((kk & 7) == c2) own = pr[c2];
+        const cpx<T> oth = swap_pair(own);
+        const cpx<T> f = h == (kk >> 3) ? own : oth;
+        unsigned key = 0u;
+        if (!used && h == (kk >> 3)) {
+          float m = (float)(fabs(f.re) + fabs(f.im));
+          if (!(m == m)) m = 0.f;                   // NaN: the row stays a candidate
+          key = ((__float_as_uint(m) >> 8) << 8) | (unsigned)(255 - row);
+        }
+        const unsigned wk = wave_max_u32(key);
+        if (wk && has && row == 255 - (int)(wk & 255u)) {
+#pragma unroll
+          for (int c2 = 0; c2 < 8; ++c2) candrow[(slot * 8 + wave) * 16 + 8 * h + c2] = pr[c2];
+        }
+        if (lane == 0) candk[slot * 8 + wave] = wk;
+        lds_barrier();
+        // the eight offers' keys in two 16-byte reads (one wait), then the
+        // pivot entry and this thread's half of the pivot row in one batch
+        const uint4* ck = reinterpret_cast<const uint4*>(candk + slot * 8);
+        const uint4 k0 = ck[0], k1 = ck[1];
+        unsigned best = k0.x;
+        int bw = 0;
+        if (k0.y > best) { best = k0.y; bw = 1; }
+        if (k0.z > best) { best = k0.z; bw = 2; }
+        if (k0.w > best) { best = k0.w; bw = 3; }
+        if (k1.x > best) { best = k1.x; bw = 4; }
+        if (k1.y > best) { best = k1.y; bw = 5; }
+        if (k1.z > best) { best = k1.z; bw = 6; }
+        if (k1.w > best) { best = k1.w; bw = 7; }
+        // an unused row below n exists for every column j < n (padding rows
+        // start out used), so p is a row below n
+        const int p = 255 - (int)(best & 255u);
+        const cpx<T>* prow = candrow + (slot * 8 + bw) * 16;
+        const cpx<T> piv = prow[kk];
+        const bool bad = (piv.re == T(0) && piv.im == T(0)) || !(piv.re == piv.re) ||
+                         !(piv.im == piv.im);
+        if (bad && tid == 0) atomicExch(flag, 1);
+        const cpx<T> inv = cinv(piv);
+        // this thread's half of the pivot row (one batch of reads)
+        cpx<T> ph[8];
+#pragma unroll
+        for (int c2 = 0; c2 < 8; ++c2) ph[c2] = prow[8 * h + c2];
+        if (has) {
+          if (row == p) {
+#pragma unroll
+            for (int c2 = 0; c2 < 8; ++c2)
+              pr[c2] = 8 * h + c2 == kk ? inv : pr[c2] * inv;
+            used = true;
+            mykk = kk;
+            if (h == 0) {
+              pivr[j] = p;
+              invp[p] = j;
+            }
+          } else {
+#pragma unroll
+            for (int c2 = 0; c2 < 8; ++c2) {
+              if (8 * h + c2 == kk) {
+                pr[c2] = -(f * inv);
+              } else {
+                const cpx<T> r2 = ph[c2] * inv;
+                cpx<T> m = pr[c2];
+                m.re = fma(-f.re, r2.re, m.re);
+                m.re = fma(f.im, r2.im, m.re);
+                m.im = fma(-f.re, r2.im, m.im);
+                m.im = fma(-f.im, r2.re, m.im);
+                pr[c2] = m;
+              }
+            }
+          }
+        }
+      }
+      // eliminated panel back to LDS; W = panel - unit vectors at the pivot
+      // rows; R rows of panel columns without a pivot (padding) are zero
+      if (has) {
+#pragma unroll
+        for (int c2 = 0; c2 < 8; ++c2) {
+          const int kc = 8 * h + c2;
+          PJ[(size_t)kc * nP + row] = pr[c2];
+          Wr[kc * ld + row] = kc == mykk ? pr[c2].re - T(1) : pr[c2].re;
+          Wi[kc * ld + row] = pr[c2].im;
+        }
+      }
+      for (int idx = tid; idx < 16 * nP; idx += 512) {
+        const int kk = idx / nP, col = idx - kk * nP;
+        if (j0 + kk >= n) {
+          Rr[kk * ld + col] = T(0);
+          Ri[kk * ld + col] = T(0);
+        }
+      }
+    }
+    lds_barrier();
+    // e. the panel's tiles take the eliminated panel; the pivot rows of the
+    //    other tiles, before their update, go to R
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int rt = wr + 2 * a, ct = wc + 4 * b;
+        if (rt >= nMt || ct >= nCt) continue;
+        if ((ct >> 1) == q) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 16 * rt + MF<T>::row(ln, i);
+            const T* srcp = reinterpret_cast<const T*>(PJ + (size_t)(8 * (ct - 2 * q) + cq) * nP + row);
+            acc[a][b][i] = srcp[pq];
+          }
+        } else {
+          // the four rows' pivot columns first (one wait), then the stores
+          int jr[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) jr[i] = invp[16 * rt + MF<T>::row(ln, i)];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int j = jr[i];
+            if ((j >> 4) == q && j < n) {
+              T* dst = pq ? Ri : Rr;
+              dst[(j & 15) * ld + 8 * ct + cq] = acc[a][b][i];
+            }
+          }
+        }
+      }
+    lds_barrier();
+    // g. M[:, rest] += W R on the matrix cores
+#pragma unroll 1
+    for (int sl = 0; sl < 4; ++sl) {
+      const int kq = 4 * sl + (ln >> 4);
+      T a1[RA], a2[RA], b1[CB], b2[CB];
+#pragma unroll
+      for (int a = 0; a < RA; ++a) {
+        const int rt = min(wr + 2 * a, nMt - 1);
+        a1[a] = Wr[kq * ld + 16 * rt + rq];
+        a2[a] = Wi[kq * ld + 16 * rt + rq];
+      }
+      // every MFMA is issued (a conditional one would keep a copy of its
+      // accumulator for the select): the panel's own tiles and tiles past
+      // the block get a zero B operand, which leaves them unchanged
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int ct = wc + 4 * b;
+        const int ctc = min(ct, nCt - 1);
+        const bool upd = ct < nCt && (ct >> 1) != q;
+        const T rr = Rr[kq * ld + 8 * ctc + cq], ri = Ri[kq * ld + 8 * ctc + cq];
+        b1[b] = upd ? (pq ? ri : rr) : T(0);
+        b2[b] = upd ? (pq ? rr : -ri) : T(0);
+      }
+#pragma unroll
+      for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          acc[a][b] = MF<T>::mfma(a1[a], b1[b], acc[a][b]);
+          acc[a][b] = MF<T>::mfma(a2[a], b2[b], acc[a][b]);
+        }
+      // one slice's operands at a time (registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();
+  // write out X[q(a)][p(b)] = M[a][b] column-major; padding rows and columns
+  // (which keep their places) are zero
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int rt = wr + 2 * a, ct = wc + 4 * b;
+      if (rt >= nMt || ct >= nCt) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * rt + MF<T>::row(lane, i), col = 8 * ct + cc;
+        const bool in = row < n && col < n;
+        // (clamped: every index is in range by construction)
+        const int r = min(max(in ? invp[row] : row, 0), nP - 1);
+        const int cl = min(max(in ? pivr[col] : col, 0), nP - 1);
+        T* dst = reinterpret_cast<T*>(Mout + (size_t)cl * nP + r);
+        dst[part] = in ? acc[a][b][i] : T(0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <class T, int RA, int CB>
+static hipError_t launch_factor_mfma_t(hdsw_ctx* c, int step, int middle) {
+  const Geometry& g = c->g;
+  int ld = g.nP;
+  while (ld % 64 != 16 && ld % 64 != 48) ld += 16;   // conflict-free operand reads
+  const size_t lds = (size_t)16 * g.nP * sizeof(cpx<T>) + (size_t)4 * 16 * ld * sizeof(T) +
+                     (size_t)(2 * g.nP + 2) * sizeof(int) + (16 + 256) * sizeof(cpx<T>) +
+                     16 * sizeof(unsigned);
+  const size_t xs = (size_t)g.K * g.nP * g.nP;
+  hipLaunchKernelGGL((k_factor_mfma<T, RA, CB>), dim3(c->nops, 2), dim3(512), lds, c->stream,
+                     (cpx<T>*)c->d_X, xs, (const cpx<T>*)c->d_coefT, c->coef_stride, c->gd,
+                     step, middle, c->d_flag, c->nops, ld);
+  return hipGetLastError();
+}
+
+// Line blocks up to 160 (complex64) or 96 (complex128) nodes: the blocked
+// inversion on the matrix cores (larger tile sets would not fit the
+// registers of two waves per SIMD); larger ones on the unblocked kernels.
+template <class T>
+static bool factor_on_mfma(hdsw_ctx* c, int step, int middle, hipError_t* e) {
+  const int nP = c->g.nP;
+  if (!c->factor_mfma) return false;
+  if (nP <= 64) { *e = launch_factor_mfma_t<T, 2, 2>(c, step, middle); return true; }
+  if (nP <= 96) { *e = launch_factor_mfma_t<T, 3, 3>(c, step, middle); return true; }
+  if constexpr (sizeof(T) == 4) {
+    if (nP <= 128) { *e = launch_factor_mfma_t<T, 4, 4>(c, step, middle); return true; }
+    if (nP <= 160) { *e = launch_factor_mfma_t<T, 5, 5>(c, step, middle); return true; }
+  }
+  return false;
+}
+
 template <class T>
 hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle) {
   const Geometry& g = c->g;
+  {
+    hipError_t e = hipSuccess;
+    if (factor_on_mfma<T>(c, step, middle, &e)) return e;
+  }
   const size_t xs = (size_t)g.K * g.nP * g.nP;
 #define HDSW_FREG(B)                                                                        \
   if (g.nP <= 32 * (B)) {                                                                   \
