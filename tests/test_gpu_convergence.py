@@ -71,3 +71,48 @@ def test_table1_setup_converges_at_second_order(H):
     _say(f"  rates {rates}")
     assert np.all(rates >= 1.8), (errs, rates)
     assert errs[-1] < 0.1
+
+
+def test_3d_constant_medium_converges_at_second_order(H):
+    # The 3D setup of Table 4 (constant medium, 3 x 3 x 3 subdomains, a
+    # smoothed point source), at k = 11 pi (the table's k / 2 pi = 11 halved,
+    # so that three meshes of 8.7 to 17.5 points per wavelength fit the
+    # plane-block path quickly): mixed solves against the free-space solution
+    # u = -exp(i k r) / (4 pi r) exp(-k^2 s^2 / 2) of eq. (helm) with the
+    # radiation condition for a unit-mass Gaussian of width s (r >> s), in
+    # the shell 0.2 < r < 0.42; layer depth fixed (W = N / 12).
+    k = 11 * np.pi
+    s = 1.0 / 24
+    meshes = (48, 72, 96)
+    errs = []
+    for N in meshes:
+        h = 1.0 / N
+        W = N // 12
+        kap = wl.constant_kappa((N,) * 3, k)
+        f = wl.gaussian_source((N,) * 3, h, (0.5, 0.5, 0.5), s)[None].astype(np.complex128)
+        _say(f"3D convergence: N = {N}, W = {W}, 3 x 3 x 3, mixed")
+        opt = H.hdsw_default_options(precision=H.HDSW_MIXED, tol=1e-10, max_iter=40)
+        ctx = H.hdsw_setup(kap, h, (3, 3, 3), W, opt,
+                           stream=torch.cuda.current_stream().cuda_stream)
+        try:
+            H.hdsw_factor(ctx)
+            ft = torch.from_numpy(f).cuda()
+            xt = torch.zeros_like(ft)
+            info, _ = H.hdsw_solve(ctx, ft, xt, 1)
+            u = xt.cpu().numpy()[0]
+            del ft, xt
+        finally:
+            H.hdsw_destroy(ctx)
+        x = (np.arange(N) + 0.5) * h
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2)
+        mask = (r > 0.2) & (r < 0.42)
+        ref = -np.exp(1j * k * r) / (4 * np.pi * r) * np.exp(-0.5 * (k * s) ** 2)
+        e = np.linalg.norm((u - ref)[mask]) / np.linalg.norm(ref[mask])
+        errs.append(e)
+        _say(f"  {info[0][0]} iterations, residual {info[0][1]:.1e}, rel L2 error {e:.3e}")
+    rates = np.log(np.array(errs[:-1]) / np.array(errs[1:])) / np.log(
+        np.array(meshes[1:]) / np.array(meshes[:-1]))
+    _say(f"  rates {rates}")
+    assert np.all(rates >= 1.8), (errs, rates)
+    assert errs[-1] < 0.1
