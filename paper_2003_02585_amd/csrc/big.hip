@@ -10,8 +10,10 @@
 //   backward  x_{K-1} = w_{K-1},   x_k = w_k - X_k (B_{k+1} x_{k+1}).
 // X_k is formed by blocked Gauss-Jordan elimination with partial pivoting
 // (largest |Re| + |Im| in the column, lowest row index on ties): a panel of
-// nb columns is eliminated by one workgroup, the rest of the matrix is
-// updated by one complex GEMM, and the column order is restored at the end.
+// nb columns is eliminated by one workgroup (in registers for blocks up to
+// 2048 nodes), the rest of the matrix takes the panel's row interchanges
+// and is updated by one complex GEMM, and the column order is restored at
+// the end.
 // Every product with a dense block is a complex GEMM on the matrix cores
 // (k_cgemm).
 #include "hdsw_internal.hpp"
@@ -37,19 +39,30 @@ constexpr int GM = 64, GN = 32, GPAD = 80;
 
 // BK-deep chunks of the sum, double-buffered in LDS (one barrier per
 // chunk): the next chunk's global loads are in flight while the current one
-// is multiplied.
+// is multiplied.  BK = 16 (complex64) or 8 (complex128) keeps the LDS of a
+// workgroup at 40 KB, so four workgroups (four waves per SIMD) share a CU
+// and hide each other's load and barrier latency; the tiled A layout keeps
+// its 64 x TK tiles (TK = 32 or 16), a chunk reading half of one.
 // Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
 // its own L2: all column tiles of a row tile are given the same XCD, so the
 // row slab of A is fetched from HBM once.  With ksplit > 1 the sum is cut
 // into ksplit parts whose raw products go to a.part and are added in a
 // fixed order by k_gemm_combine (results do not depend on timing).
+template <class T>
+constexpr int gemm_tk() { return sizeof(T) == 4 ? 32 : 16; }
+
 template <class T, int BK, bool TILED>
 __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
+  constexpr int TK = gemm_tk<T>();
+  static_assert(TK % BK == 0, "a chunk lies inside one A tile");
   typedef typename MF<T>::v4 v4;
   constexpr int AL = BK / 4;                 // A elements per thread
   constexpr int BL = BK / 8;                 // B elements per thread
-  __shared__ cpx<T> As[2][BK][GPAD];         // [buf][k][row]
-  __shared__ cpx<T> Bp[2][BK][GPAD];         // [buf][k][4 groups x 16 operand columns]
+  // A chunks [buf][k][row] and B operand pairs [buf][k][4 groups x 16
+  // operand columns], then the output tile staged over both
+  __shared__ cpx<T> smem[4 * BK * GPAD];
+  cpx<T>(*As)[BK][GPAD] = reinterpret_cast<cpx<T>(*)[BK][GPAD]>(smem);
+  cpx<T>(*Bp)[BK][GPAD] = reinterpret_cast<cpx<T>(*)[BK][GPAD]>(smem + 2 * BK * GPAD);
   const int z = blockIdx.z / a.ksplit, kpart = blockIdx.z - z * a.ksplit;
   const int xcd = blockIdx.x & 7, pos = blockIdx.x >> 3;
   const int rtile = xcd + 8 * (pos / nct), ctile = pos - (pos / nct) * nct;
@@ -80,7 +93,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
   const int ar = tid & 63, ak = (tid >> 6) * AL;
   const bool arow_ok = row0 + ar < a.M;
   const cpx<T>* acol = A + (arow_ok ? row0 + ar : 0);
-  const cpx<T>* atile = TILED ? A + (long long)a.a_rt[rtile] * a.a_tile_ld * (GM * BK) : nullptr;
+  const cpx<T>* atile = TILED ? A + (long long)a.a_rt[rtile] * a.a_tile_ld * (GM * TK) : nullptr;
 
   cpx<T> ra[AL], rb[BL];
   v4 accR[4], accI[4];
@@ -97,7 +110,8 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
 #define HDSW_GEMM_LOAD(k0)                                                       \
   {                                                                              \
     if (TILED) {                                                                 \
-      const cpx<T>* tp = atile + (long long)a.a_kt[(k0) / BK] * (GM * BK) + ar;  \
+      const cpx<T>* tp = atile + (long long)a.a_kt[(k0) / TK] * (GM * TK) +      \
+                         ((k0) % TK) * GM + ar;                                  \
       /* field by field: a complex128 struct copy goes through private */      \
       /* memory here */                                                          \
       _Pragma("unroll") for (int u = 0; u < AL; ++u) {                           \
@@ -154,10 +168,10 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
 #undef HDSW_GEMM_LOAD
 #undef HDSW_GEMM_STORE
 
-  // stage [Re | Im] halves as complex columns (reusing the A buffers)
-  cpx<T>(*Cs)[GM] = reinterpret_cast<cpx<T>(*)[GM]>(&As[0][0][0]);
-  static_assert(sizeof(As) >= sizeof(cpx<T>) * GN * GM, "staging does not fit");
-  T* cs = reinterpret_cast<T*>(&As[0][0][0]);
+  // stage [Re | Im] halves as complex columns (reusing the operand buffers)
+  cpx<T>(*Cs)[GM] = reinterpret_cast<cpx<T>(*)[GM]>(smem);
+  static_assert(sizeof(smem) >= sizeof(cpx<T>) * GN * GM, "staging does not fit");
+  T* cs = reinterpret_cast<T*>(smem);
   const int part = mc >> 3, cc = mc & 7;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
@@ -200,9 +214,10 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs a, int nrt, int nct) {
   }
 }
 
+// k extent of one tile of a tiled A operand
 template <class T>
 int gemm_bk() {
-  return sizeof(T) == 4 ? 32 : 16;
+  return gemm_tk<T>();
 }
 
 // Skinny product (at most 8 columns per group), HBM-bound: each wave
@@ -352,10 +367,11 @@ hipError_t gemm(hipStream_t st, const GemmArgs& a_in, int maxcols, int ngroups) 
   if (a.ksplit < 1) a.ksplit = 1;
   if (a.ksplit > 1 && !a.part) return hipErrorInvalidValue;
   a.part_cols = maxcols;
-  constexpr int BK = sizeof(T) == 4 ? 32 : 16;
+  constexpr int BK = sizeof(T) == 4 ? 16 : 8;
+  constexpr int TK = gemm_tk<T>();
   const int nrt = (a.M + GM - 1) / GM, nct = (maxcols + GN - 1) / GN;
   // at most 8 columns per group: the product streams A (HBM-bound)
-  if (maxcols <= 8 && a.ksplit == 1 && !a.no_skinny && (!a.a_rt || BK == 32)) {
+  if (maxcols <= 8 && a.ksplit == 1 && !a.no_skinny && (!a.a_rt || TK == 32)) {
     dim3 g2(8 * ((nrt + 7) / 8), ngroups, 1);
     if (a.a_rt) {
       if (a.M % GM != 0) return hipErrorInvalidValue;
@@ -368,7 +384,7 @@ hipError_t gemm(hipStream_t st, const GemmArgs& a_in, int maxcols, int ngroups) 
   dim3 grid(8 * ((nrt + 7) / 8) * nct, 1, ngroups * a.ksplit);
   if (a.a_rt) {
     // tiled A: whole tiles only
-    if (a.M % GM != 0 || a.Kd % BK != 0) return hipErrorInvalidValue;
+    if (a.M % GM != 0 || a.Kd % TK != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_cgemm<T, BK, true>), grid, dim3(256), 0, st, a, nrt, nct);
   } else {
     hipLaunchKernelGGL((k_cgemm<T, BK, false>), grid, dim3(256), 0, st, a, nrt, nct);
@@ -503,6 +519,251 @@ __global__ void k_gj_colperm(cpx<T>* X, long long sz, int n, const int* piv) {
   }
 }
 
+// Register-resident panel (n <= 1024 S): one workgroup of 1024 threads per
+// matrix z eliminates the pivots j0 .. j0 + nbr - 1 (nbr <= NB) on the panel
+// columns only, thread t holding rows t + 1024 s (s < S) of the NB panel
+// columns in registers.  Rows are not moved while the panel is eliminated:
+// the pivot of column j0 + q is the row with the largest |Re| + |Im| (its
+// exponent and leading 10 mantissa bits, then the lowest row) among the rows
+// at positions >= j0 not chosen yet, which are exactly the candidate
+// positions of the row-swapping algorithm.  One barrier per pivot: every
+// wave finds its best row by cross-lane moves and offers it (key and the
+// row's NB entries) in LDS; every thread then takes the best of the 16
+// offers.  Offers alternate between two buffers by pivot parity, so a
+// pivot's offers never overwrite ones still being read.
+// At the end the chosen rows are turned into the interchanges of the
+// swapping algorithm (position j0 + q with position piv[j0 + q]) and the
+// panel is written back with every row at its interchanged position.  The
+// interchanges' net effect on any other column is a set of at most 2 NB
+// moves (row at position src goes to position dst), written to mv for the
+// kernels that bring the other columns along.
+template <int NB>
+__host__ __device__ constexpr int gj_mv_stride() { return 1 + 4 * NB; }
+
+// Applies the moves of one panel (list m: count, destinations, sources) to a
+// column: every source is read before any destination is written.
+template <class T, int NB>
+__device__ __forceinline__ void gj_apply_moves(cpx<T>* col, const int* m) {
+  // field by field: a conditional complex128 struct copy would go through
+  // private memory
+  const int cnt = m[0];
+  T vr[2 * NB], vi[2 * NB];
+#pragma unroll
+  for (int e = 0; e < 2 * NB; ++e) {
+    vr[e] = T(0);
+    vi[e] = T(0);
+    if (e < cnt) {
+      const cpx<T>* s = col + m[1 + 2 * NB + e];
+      vr[e] = s->re;
+      vi[e] = s->im;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 2 * NB; ++e)
+    if (e < cnt) {
+      cpx<T>* d = col + m[1 + e];
+      d->re = vr[e];
+      d->im = vi[e];
+    }
+}
+
+template <class T, int NB, int S>
+__global__ __launch_bounds__(1024) void k_gj_panel_reg(cpx<T>* X, long long sz, int n, int j0,
+                                                       int nbr, int* piv, int* flag, int* mv,
+                                                       long long mvso) {
+  __shared__ cpx<T> offer[2][16][NB];
+  __shared__ __align__(16) unsigned okey[2][16];
+  __shared__ int obad[2][16];                  // the offered pivot is zero or NaN
+  __shared__ int prow_of[NB];                  // row chosen for column j0 + q
+  __shared__ int mrow[2 * NB], mpos[2 * NB];   // moved rows and their positions
+  __shared__ int mcnt;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  cpx<T>* A = X + (long long)blockIdx.x * sz;
+  cpx<T> pr[S][NB];
+  bool cand[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = tid + 1024 * s;
+    cand[s] = i < n && i >= j0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      pr[s][c] = mk<T>(T(0), T(0));
+      if (i < n && c < nbr) pr[s][c] = A[(long long)(j0 + c) * n + i];
+    }
+  }
+  // the pivot loop is unrolled: column q of the panel is a static register
+  // index in every step
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (q >= nbr) continue;
+    const int slot = q & 1;
+    unsigned key = 0u;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (cand[s]) {
+        float m = (float)(fabs(pr[s][q].re) + fabs(pr[s][q].im));
+        if (!(m == m)) m = 0.f;                  // NaN: the row stays a candidate
+        const unsigned k = (__float_as_uint(m) & ~8191u) | (unsigned)(8191 - (tid + 1024 * s));
+        key = k > key ? k : key;
+      }
+    }
+    const unsigned wk = wave_max_u32(key);
+    // the wave's best row offers itself already scaled as the pivot row
+    // (entry q: the inverse of the pivot, the others: entry x inverse)
+    if (wk) {
+      const int wrow = 8191 - (int)(wk & 8191u);
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        if (wrow == tid + 1024 * s) {
+          const cpx<T> pv = pr[s][q];
+          const bool bad = (pv.re == T(0) && pv.im == T(0)) || !(pv.re == pv.re) ||
+                           !(pv.im == pv.im);
+          const cpx<T> inv = bad ? mk<T>(T(0), T(0)) : cinv(pv);
+#pragma unroll
+          for (int c = 0; c < NB; ++c) offer[slot][wave][c] = c == q ? inv : pr[s][c] * inv;
+          obad[slot][wave] = bad ? 1 : 0;
+        }
+    }
+    if (lane == 0) okey[slot][wave] = wk;
+    lds_barrier();
+    const uint4* ok4 = reinterpret_cast<const uint4*>(okey[slot]);
+    unsigned best = 0u;
+    int bw = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint4 kv = ok4[v];
+      if (kv.x > best) { best = kv.x; bw = 4 * v; }
+      if (kv.y > best) { best = kv.y; bw = 4 * v + 1; }
+      if (kv.z > best) { best = kv.z; bw = 4 * v + 2; }
+      if (kv.w > best) { best = kv.w; bw = 4 * v + 3; }
+    }
+    // a candidate exists for every column (n - j0 - q rows), so best > 0
+    const int p = 8191 - (int)(best & 8191u);
+    const cpx<T>* ph = offer[slot][bw];
+    if (tid == 0) {
+      if (obad[slot][bw]) atomicExch(flag, 1);
+      prow_of[q] = p;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = tid + 1024 * s;
+      if (i == p) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) pr[s][c] = ph[c];
+        cand[s] = false;
+      } else if (i < n) {
+        const cpx<T> f = pr[s][q];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const cpx<T> r2 = ph[c];
+          if (c == q) {
+            pr[s][c] = -(f * r2);
+          } else {
+            cpx<T> m = pr[s][c];
+            m.re = fma(-f.re, r2.re, m.re);
+            m.re = fma(f.im, r2.im, m.re);
+            m.im = fma(-f.re, r2.im, m.im);
+            m.im = fma(-f.im, r2.re, m.im);
+            pr[s][c] = m;
+          }
+        }
+      }
+    }
+  }
+  lds_barrier();
+  // the interchanges: position j0 + q swaps with the position its pivot
+  // row holds at that point; only the rows of the swaps move
+  if (tid == 0) {
+    int cnt = 0;
+    for (int q = 0; q < nbr; ++q) {
+      const int pr_ = prow_of[q], a = j0 + q;
+      int rq = pr_, y = a, ip = -1, iy = -1;
+      for (int e = 0; e < cnt; ++e) {
+        if (mrow[e] == pr_) { rq = mpos[e]; ip = e; }
+        if (mpos[e] == a) { y = mrow[e]; iy = e; }
+      }
+      piv[(long long)blockIdx.x * n + a] = rq;
+      if (rq != a) {
+        if (ip < 0) { ip = cnt++; mrow[ip] = pr_; }
+        mpos[ip] = a;
+        if (iy < 0) { iy = cnt++; mrow[iy] = y; }
+        mpos[iy] = rq;
+      }
+    }
+    mcnt = cnt;
+    // the moves for the other columns: [count, destinations, sources]
+    int* m = mv + (long long)blockIdx.x * mvso;
+    m[0] = cnt;
+    for (int e = 0; e < cnt; ++e) {
+      m[1 + e] = mpos[e];
+      m[1 + 2 * NB + e] = mrow[e];
+    }
+  }
+  lds_barrier();
+  const int cnt = mcnt;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = tid + 1024 * s;
+    if (i >= n) continue;
+    int pos = i;
+    for (int e = 0; e < cnt; ++e)
+      if (mrow[e] == i) pos = mpos[e];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nbr) A[(long long)(j0 + c) * n + pos] = pr[s][c];
+  }
+}
+
+// Inner update of a two-level panel: after the register panel of columns
+// j0 .. j0 + nbr - 1, every other column j of the outer panel J0 .. J0 +
+// OBr - 1 takes the panel's moves, its rows j0 .. j0 + nbr - 1 (r) are
+// taken out and zeroed, and the column is updated by the eliminated panel
+// E (those columns of X): col += E r.  One workgroup per (column, matrix);
+// a plain sum over the panel's nbr columns per row.
+template <class T, int NB>
+__global__ __launch_bounds__(256) void k_gj_inner(cpx<T>* X, long long sz, int n, int J0, int j0,
+                                                  int nbr, const int* mv, long long mvso) {
+  __shared__ cpx<T> r[NB];
+  const int z = blockIdx.y, j = J0 + blockIdx.x, tid = threadIdx.x;
+  if (j >= j0 && j < j0 + nbr) return;
+  cpx<T>* A = X + (long long)z * sz;
+  cpx<T>* col = A + (long long)j * n;
+  const cpx<T>* E = A + (long long)j0 * n;
+  if (tid == 0) gj_apply_moves<T, NB>(col, mv + (long long)z * mvso);
+  __syncthreads();
+  if (tid < nbr) {
+    r[tid] = col[j0 + tid];
+    col[j0 + tid] = mk<T>(T(0), T(0));
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 256) {
+    cpx<T> acc = col[i];
+    for (int q = 0; q < nbr; ++q) acc = acc + E[(long long)q * n + i] * r[q];
+    col[i] = acc;
+  }
+}
+
+// Outer rows of a two-level panel: thread j of matrix z (blockIdx.y), for a
+// column j outside the outer panel J0 .. J0 + OBr - 1, applies the moves of
+// the npan inner panels in order, moves its rows J0 .. J0 + OBr - 1 to R_z
+// (OBr x n, leading dimension OBr) and zeroes them.  The rest of the matrix
+// is then A += E R with E the outer panel's columns.
+template <class T, int NB>
+__global__ void k_gj_outer_rows(cpx<T>* X, long long sz, int n, int J0, int OBr, int npan,
+                                const int* mv, long long mvso, cpx<T>* R, long long sR) {
+  const int z = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || (j >= J0 && j < J0 + OBr)) return;
+  cpx<T>* col = X + (long long)z * sz + (long long)j * n;
+  const int* mz = mv + (long long)z * mvso;
+  for (int p = 0; p < npan; ++p) gj_apply_moves<T, NB>(col, mz + p * gj_mv_stride<NB>());
+  cpx<T>* Rz = R + (long long)z * sR + (long long)j * OBr;
+  for (int q = 0; q < OBr; ++q) {
+    Rz[q] = col[J0 + q];
+    col[J0 + q] = mk<T>(T(0), T(0));
+  }
+}
+
 // ------------------------------------------------------------ factor
 // Dense D_k of every distinct operator (3D, plane k) written into its X_k
 // slot: the in-plane 5-point part of the operator minus
@@ -543,6 +804,28 @@ __global__ void k_form_plane(cpx<T>* X, const cpx<T>* coefT, size_t cstride, Geo
 }
 
 // rbuf: 2 n 32 elements per distinct operator (panel rows R and columns E)
+// Two-level panels for blocks up to 2048 nodes: outer panels of OB = 64
+// columns, each eliminated as inner panels of NBR columns in registers
+// (k_gj_panel_reg) whose updates reach only the outer panel's other
+// columns (k_gj_inner); the rest of the matrix then takes the outer panel's
+// moves and one rank-64 complex GEMM.  Larger blocks: 32-column panels
+// eliminated in global memory (k_gj_panel) and a rank-32 GEMM each.
+constexpr int kGjOuter = 64;
+template <class T>
+constexpr int gj_inner_nb() { return sizeof(T) == 4 ? 16 : 8; }
+static bool gj_two_level(int n) { return n <= 2048; }
+
+// Scratch of launch_big_factor: the R rows of every operator, then (two
+// levels) the inner panels' move lists.
+template <class T>
+size_t big_factor_scratch_bytes(const hdsw_ctx* c) {
+  const size_t n = c->g.n, nops = c->nops;
+  if (!gj_two_level((int)n)) return nops * 2 * n * 32 * sizeof(cpx<T>);
+  constexpr int NBR = gj_inner_nb<T>();
+  const size_t mvso = (size_t)(kGjOuter / NBR) * gj_mv_stride<NBR>();
+  return nops * kGjOuter * n * sizeof(cpx<T>) + nops * mvso * sizeof(int) + 256;
+}
+
 template <class T>
 hipError_t launch_big_factor(hdsw_ctx* c, void* rbuf) {
   const Geometry& g = c->g;
@@ -551,7 +834,11 @@ hipError_t launch_big_factor(hdsw_ctx* c, void* rbuf) {
   const long long sz = (long long)g.K * nn;     // operator stride in X
   cpx<T>* X = (cpx<T>*)c->d_X;
   cpx<T>* R = (cpx<T>*)rbuf;
-  const int nb = 32;
+  constexpr int NBR = gj_inner_nb<T>();
+  const bool two = gj_two_level(n);
+  const long long sR = two ? (long long)kGjOuter * n : 2LL * n * 32;   // R per operator
+  const long long mvso = (long long)(kGjOuter / NBR) * gj_mv_stride<NBR>();
+  int* mv = reinterpret_cast<int*>(R + (size_t)nops * sR);
   for (int k = 0; k < g.K; ++k) {
     int blocks = (int)std::min<long long>((nn + 255) / 256, 1 << 16);
     hipLaunchKernelGGL(k_form_plane<T>, dim3(blocks, nops), dim3(256), 0, c->stream, X,
@@ -560,35 +847,74 @@ hipError_t launch_big_factor(hdsw_ctx* c, void* rbuf) {
     if (e != hipSuccess) return e;
     cpx<T>* Xk = X + (long long)k * nn;
     int* piv = c->d_piv;
-    for (int j0 = 0; j0 < n; j0 += nb) {
-      int nbr = std::min(nb, n - j0);
-      hipLaunchKernelGGL(k_gj_panel<T>, dim3(nops), dim3(1024), 0, c->stream, Xk, sz, n, j0,
-                         nbr, piv, c->d_flag);
-      long long tot = (long long)n * nbr;
-      int tb = (int)std::min<long long>((tot + 255) / 256, 1 << 16);
-      hipLaunchKernelGGL(k_gj_take_rows<T>, dim3(tb, nops), dim3(256), 0, c->stream, Xk, sz,
-                         n, j0, nbr, R, 2LL * n * nb, (long long)n * nb);
+    const int ob = two ? kGjOuter : 32;
+    for (int J0 = 0; J0 < n; J0 += ob) {
+      const int OBr = std::min(ob, n - J0);
+      if (two) {
+        const int npan = (OBr + NBR - 1) / NBR;
+        for (int p = 0; p < npan; ++p) {
+          const int j0 = J0 + p * NBR, nbr = std::min(NBR, J0 + OBr - j0);
+          int* mvp = mv + p * gj_mv_stride<NBR>();
+          if (n <= 1024)
+            hipLaunchKernelGGL((k_gj_panel_reg<T, NBR, 1>), dim3(nops), dim3(1024), 0,
+                               c->stream, Xk, sz, n, j0, nbr, piv, c->d_flag, mvp, mvso);
+          else
+            hipLaunchKernelGGL((k_gj_panel_reg<T, NBR, 2>), dim3(nops), dim3(1024), 0,
+                               c->stream, Xk, sz, n, j0, nbr, piv, c->d_flag, mvp, mvso);
+          if (OBr > nbr)
+            hipLaunchKernelGGL((k_gj_inner<T, NBR>), dim3(OBr, nops), dim3(256), 0, c->stream,
+                               Xk, sz, n, J0, j0, nbr, (const int*)mvp, mvso);
+        }
+        hipLaunchKernelGGL((k_gj_outer_rows<T, NBR>), dim3((n + 255) / 256, nops), dim3(256),
+                           0, c->stream, Xk, sz, n, J0, OBr, npan, (const int*)mv, mvso, R, sR);
+      } else {
+        hipLaunchKernelGGL(k_gj_panel<T>, dim3(nops), dim3(1024), 0, c->stream, Xk, sz, n, J0,
+                           OBr, piv, c->d_flag);
+        long long tot = (long long)n * OBr;
+        int tb = (int)std::min<long long>((tot + 255) / 256, 1 << 16);
+        hipLaunchKernelGGL(k_gj_take_rows<T>, dim3(tb, nops), dim3(256), 0, c->stream, Xk, sz,
+                           n, J0, OBr, R, sR, (long long)n * 32);
+      }
       e = hipGetLastError();
       if (e != hipSuccess) return e;
-      GemmArgs a{};
-      a.M = n;
-      a.N = n;
-      a.Kd = nbr;
-      a.A = R + (long long)n * nb;
-      a.lda = n;
-      a.sAz = 2LL * n * nb;
-      a.B = R;
-      a.ldb = nbr;
-      a.sb = 0;
-      a.sBz = 2LL * n * nb;
-      a.C = Xk;
-      a.ldc = n;
-      a.sc = 0;
-      a.sCz = sz;
-      a.cpb = n;
-      a.neg = 0;
-      a.beta = 1;
-      e = gemm<T>(c->stream, a, n, nops);
+      // rest of the matrix += E R (two levels: E = the outer panel's
+      // columns of X, and the columns left and right of it; one level: E
+      // copied beside R, every column, R zero in the panel's columns)
+      auto update = [&](int c0, int ncols) -> hipError_t {
+        if (ncols <= 0) return hipSuccess;
+        GemmArgs a{};
+        a.M = n;
+        a.N = ncols;
+        a.Kd = OBr;
+        if (two) {
+          a.A = Xk + (long long)J0 * n;
+          a.sAz = sz;
+          a.B = R + (long long)c0 * OBr;
+          a.ldb = OBr;
+        } else {
+          a.A = R + (long long)n * 32;
+          a.sAz = sR;
+          a.B = R;
+          a.ldb = OBr;
+        }
+        a.lda = n;
+        a.sb = 0;
+        a.sBz = sR;
+        a.C = Xk + (long long)c0 * n;
+        a.ldc = n;
+        a.sc = 0;
+        a.sCz = sz;
+        a.cpb = ncols;
+        a.neg = 0;
+        a.beta = 1;
+        return gemm<T>(c->stream, a, ncols, nops);
+      };
+      if (two) {
+        e = update(0, J0);
+        if (e == hipSuccess) e = update(J0 + OBr, n - J0 - OBr);
+      } else {
+        e = update(0, n);
+      }
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_gj_colperm<T>, dim3((n + 255) / 256, nops), dim3(256), 0, c->stream,
@@ -750,6 +1076,7 @@ hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int
   template int gemm_bk<T>();                                                               \
   template hipError_t launch_extract_tiled<T>(hdsw_ctx*, int, int, int);                   \
   template hipError_t launch_big_factor<T>(hdsw_ctx*, void*);                              \
+  template size_t big_factor_scratch_bytes<T>(const hdsw_ctx*);                             \
   template hipError_t launch_big_solve<T>(hdsw_ctx*, int, const int*, const int*,          \
                                           const int*, const int*, const int*, int, int, int);
 HDSW_INST3(float)

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <map>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 
@@ -148,11 +149,26 @@ static uint64_t fnv1a(const void* data, size_t n) {
   return h;
 }
 
+// ------------------------------------------------------------ runtime lock
+// Runtime calls that may wait on other streams or on the whole device
+// (allocation and free, blocking copies, creation and destruction of
+// streams, events and graphs) fail while another thread records a graph,
+// and a graph being recorded can be invalidated by them.  Contexts may be
+// driven from several threads (a serving loop factors new operators on a
+// worker thread while the main thread records DDM applications), so these
+// calls and the recording of an application hold one process-wide lock.
+static std::recursive_mutex& rt_mu() {
+  static std::recursive_mutex m;
+  return m;
+}
+typedef std::lock_guard<std::recursive_mutex> RtGuard;
+
 // ------------------------------------------------------------ memory
 // Every device allocation of a context goes through these two: the caller's
 // allocator hooks when hdsw_options sets them (so a framework's caching
 // allocator can own the memory), hipMalloc / hipFree otherwise.
 static void raw_free(const hdsw_ctx* c, void* p) {
+  RtGuard lk(rt_mu());
   if (c->opt.dev_free) c->opt.dev_free(p, c->opt.alloc_ctx);
   else (void)hipFree(p);
 }
@@ -160,6 +176,7 @@ static hdsw_status dev_alloc(hdsw_ctx* c, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
   if (c->opt.hbm_budget && c->alloc_bytes + bytes > c->opt.hbm_budget) return HDSW_ENOMEM;
+  RtGuard lk(rt_mu());
   if (c->opt.dev_alloc) {
     *p = c->opt.dev_alloc(bytes, c->opt.alloc_ctx);
     if (!*p) return HDSW_ENOMEM;
@@ -257,6 +274,7 @@ struct TimedScope {
     if (!((c->tm.mask >> cls) & 1)) return;
     EvPool& p = pools()[c];
     if (p.ev.empty()) {
+      RtGuard lk(rt_mu());
       p.ev.resize(2 * 8192, nullptr);
       for (auto& e : p.ev)
         if (hipEventCreate(&e) != hipSuccess) e = nullptr;
@@ -620,6 +638,7 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
     std::copy(kops[o].begin(), kops[o].end(), kflat.begin() + (size_t)o * g.sub_nodes);
   hipError_t he = hipSuccess;
   auto up = [&](void* dst, const void* src, size_t bytes) {
+    RtGuard lk(rt_mu());
     if (he == hipSuccess) he = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   };
   up(c->d_kappa_sub, kflat.data(), kflat.size() * sizeof(double));
@@ -669,7 +688,7 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
   } else {
     // plane blocks: one dense inversion per plane, all operators together
     void* rbuf = nullptr;
-    ACHK(dev_alloc(c, &rbuf, (size_t)c->nops * 2 * g.n * 32 * sizeof(cpx<T>)));
+    ACHK(dev_alloc(c, &rbuf, big_factor_scratch_bytes<T>(c)));
     hipError_t fe;
     {
       double fl = 8.0 * g.n * (double)g.n * g.n * g.K * c->nops;
@@ -725,7 +744,11 @@ static hdsw_status factor_impl(hdsw_ctx* c) {
   c->d_panel = saved;
   dev_free(c, tmp);
   int flag = 0;
-  HCHK(hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  {
+    RtGuard lk(rt_mu());
+    HCHK(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HCHK(hipStreamSynchronize(c->stream));
+  }
   if (flag) return HDSW_EINVAL;  // a singular diagonal block
   c->factored = true;
   return HDSW_OK;
@@ -863,6 +886,7 @@ static hdsw_status ddm_eager(hdsw_ctx* c, const c128* r, c128* out, int C, int a
 }
 
 static void graphs_clear(hdsw_ctx* c) {
+  RtGuard lk(rt_mu());
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   c->graph_seen.clear();
@@ -889,9 +913,12 @@ static hdsw_status ddm(hdsw_ctx* c, const c128* r, c128* out, int C, int accumul
       return ddm_eager(c, r, out, C, accumulate);
     }
     if (c->graphs.size() >= 64) graphs_clear(c);
+    RtGuard lk(rt_mu());
     if (!c->cap_stream) HCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    // A capture can be refused or invalidated by the runtime (for example
-    // by another thread's work on the legacy default stream).  Nothing
+    // The recording holds the runtime lock, so this library's own
+    // allocations, frees and blocking copies on other threads wait for it.
+    // A capture can still be refused or invalidated by the runtime (for
+    // example by other work on the legacy default stream).  Nothing
     // recorded ran, so the application then runs eagerly and the key stays
     // eager; errors seen while recording are not device errors.
     const hdsw_status sticky0 = c->sticky;
@@ -1094,6 +1121,7 @@ hdsw_status batch_reserve(hdsw_ctx* c, int cap) {
   if (cap < 1) return HDSW_EINVAL;
   if (c->nact > 0) return HDSW_EBUSY;
   ACHK(ensure_ws(c, cap, false));
+  RtGuard lk(rt_mu());
   if (!c->h_norm || cap > c->batch_cap) {
     if (c->h_norm) (void)hipHostFree(c->h_norm);
     c->h_norm = nullptr;
@@ -1246,6 +1274,7 @@ hdsw_status tuning_set(hdsw_ctx* c, const TuneParams& t) {
 
 void destroy(hdsw_ctx* c) {
   if (!c) return;
+  RtGuard lk(rt_mu());
   graphs_clear(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->h_norm) (void)hipHostFree(c->h_norm);

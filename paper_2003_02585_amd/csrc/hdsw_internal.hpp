@@ -357,6 +357,8 @@ template <class T>
 hipError_t launch_face_coef(hdsw_ctx* c);
 template <class T>
 hipError_t launch_big_factor(hdsw_ctx* c, void* rbuf);
+template <class T>
+size_t big_factor_scratch_bytes(const hdsw_ctx* c);
 hipError_t launch_rhs_from_f(hdsw_ctx* c, const c128* f, c128* b, int C);
 hipError_t launch_residual(hdsw_ctx* c, const c128* b, const c128* x, c128* r,
                            int C);

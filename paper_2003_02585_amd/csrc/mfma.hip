@@ -872,26 +872,6 @@ __device__ __forceinline__ double swap_pair_f(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-// Largest value over the 64 lanes of the wave, returned in every lane:
-// quad permutations and row mirrors reduce each row of 16 lanes, row
-// broadcasts combine the rows into lane 63.
-__device__ __forceinline__ unsigned dpp_max(unsigned v, unsigned t) { return v > t ? v : t; }
-__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
-  const int iv = (int)v;
-  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(iv, iv, 0xB1, 0xF, 0xF, false));
-  int w = (int)v;
-  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x4E, 0xF, 0xF, false));
-  w = (int)v;
-  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x141, 0xF, 0xF, false));
-  w = (int)v;
-  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x140, 0xF, 0xF, false));
-  w = (int)v;
-  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x142, 0xA, 0xF, false));
-  w = (int)v;
-  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x143, 0xC, 0xF, false));
-  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
-}
-
 // The value of lane l (wave-uniform) of v, into a scalar register.
 __device__ __forceinline__ float rdlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -914,7 +894,6 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
                                                      GeoDev g, int step, int middle, int* flag,
                                                      int nops, int ld) {
   typedef typename MF<T>::v4 v4;
-  constexpr int RS = (32 * RA + 63) / 64;        // panel rows per lane of the eliminating wave
   extern __shared__ unsigned char smem_raw[];
   const int op = blockIdx.x, half = blockIdx.y;
   if (op >= nops) return;

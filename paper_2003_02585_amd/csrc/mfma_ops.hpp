@@ -1,4 +1,5 @@
-// Matrix-core (MFMA) wrappers for gfx950 shared by the kernel files.
+// Matrix-core (MFMA) and cross-lane wrappers for gfx950 shared by the
+// kernel files.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,5 +26,25 @@ struct MF<double> {
   // accumulator register i of lane l holds row l / 16 + 4 i, column l % 16
   static __device__ inline int row(int l, int i) { return (l >> 4) + 4 * i; }
 };
+
+// Largest value over the 64 lanes of the wave, returned in every lane:
+// quad permutations and row mirrors reduce each row of 16 lanes, row
+// broadcasts combine the rows into lane 63.
+__device__ __forceinline__ unsigned dpp_max(unsigned v, unsigned t) { return v > t ? v : t; }
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  const int iv = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(iv, iv, 0xB1, 0xF, 0xF, false));
+  int w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x4E, 0xF, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x141, 0xF, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x140, 0xF, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x142, 0xA, 0xF, false));
+  w = (int)v;
+  v = dpp_max(v, (unsigned)__builtin_amdgcn_update_dpp(w, w, 0x143, 0xC, 0xF, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
 
 }  // namespace hdsw
