@@ -615,8 +615,10 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
         }
         c->sg_n.push_back(ng);
         c->sg_maxcnt.push_back(mx);
+        c->gpart_per_col = std::max(c->gpart_per_col, (size_t)ng * mx * mpad);
       }
     }
+    c->gpart_per_col = std::max(c->gpart_per_col, (size_t)c->nops * c->grp_maxcnt * g.n);
     if (fmap.empty()) fmap.push_back(0);
     if (sg_op.empty()) { sg_op.push_back(0); sg_off.push_back(0); sg_cnt.push_back(0); }
     if (sg_ids.empty()) sg_ids.push_back(0);
@@ -793,9 +795,9 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
       // the step GEMM's B operand: trace sources in the padded k space of T
       WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) * (size_t)c->t_nkt * c->t_tk * e);
       WALLOC(c->d_out, iface);
-      // split-sum partials of the plane solves: up to 4 parts of every
-      // operator group's columns
-      size_t gp = (size_t)4 * c->nops * c->grp_maxcnt * C * g.n * e;
+      // split-sum partials of the plane solves and step GEMMs: up to 4
+      // parts of every operator group's columns
+      size_t gp = (size_t)4 * c->gpart_per_col * C * e;
       WALLOC(c->d_gpart, gp);
       c->gpart_bytes = gp;
     }
@@ -969,7 +971,7 @@ static size_t max_cols(hdsw_ctx* c) {
                    (size_t)g.nsub * g.NI * e * (c->sch.nsweeps + (g.dim == 3 ? 4 : 2)) +
                    3 * (size_t)g.glob_nodes * sizeof(c128);
   if (c->opt.gmres_m > 0) per_col += (size_t)(2 * c->opt.gmres_m + 1) * g.glob_nodes * sizeof(c128);
-  if (g.dim == 3) per_col += (size_t)4 * c->nops * c->grp_maxcnt * g.n * e;
+  if (g.dim == 3) per_col += (size_t)4 * c->gpart_per_col * e;
   size_t used = c->alloc_bytes;
   // workspaces currently held can be reused
   if (c->Cmax > 0) used -= std::min(used, (size_t)c->Cmax * per_col);

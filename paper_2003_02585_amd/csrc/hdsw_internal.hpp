@@ -232,6 +232,9 @@ struct hdsw_ctx {
   int t_roff[6] = {0}, t_koff[6] = {0};         // padded face offsets
   int* d_tmap = nullptr;                        // per sweep: row tiles, k tiles, row map
   std::vector<int> tm_rt_off, tm_kt_off, tm_row_off, tm_nrt, tm_nkt, tm_mpad;
+  // 3D split-sum partials per right-hand-side column (elements, one part):
+  // the larger of the plane solves' and the step GEMMs' needs
+  size_t gpart_per_col = 0;
 
 
   // precision-dependent factors: element type cpx<float> or cpx<double>

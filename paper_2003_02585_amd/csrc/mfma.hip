@@ -1798,7 +1798,18 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
     } else {
       if (tk != gemm_bk<T>()) return hipErrorInvalidValue;
       a.no_skinny = c->tune.gemm_skinny == 2;
-      hipError_t e = gemm<T>(c->stream, a, c->sg_maxcnt[sidx] * C, c->sg_n[sidx]);
+      // fewer row tiles than the CUs hold workgroups (four each): split the
+      // sum, from the step's shape only (rows and operator groups); the
+      // streaming kernel of narrow products keeps one part
+      const int maxcols = c->sg_maxcnt[sidx] * C;
+      const bool skinny = maxcols <= 8 && !a.no_skinny;
+      const long long rtiles = (long long)(a.M / 64) * c->sg_n[sidx];
+      int ks = skinny ? 1 : (int)std::min<long long>(4, std::max<long long>(1, (1024 + rtiles - 1) / rtiles));
+      while (ks > 1 && (size_t)ks * c->sg_n[sidx] * maxcols * a.M * sizeof(cpx<T>) > c->gpart_bytes)
+        --ks;
+      a.ksplit = ks;
+      a.part = c->d_gpart;
+      hipError_t e = gemm<T>(c->stream, a, maxcols, c->sg_n[sidx]);
       if (e != hipSuccess) return e;
     }
     long long tot = (long long)cnt * C * nout;

@@ -76,7 +76,7 @@ static Carve carve(const hdsw_ctx* c, int C) {
     k.out = o;
     o += align256(iface);
     k.gpart = o;
-    k.gpart_bytes = (size_t)4 * c->nops * c->grp_maxcnt * C * g.n * e;
+    k.gpart_bytes = (size_t)4 * c->gpart_per_col * C * e;
     o += align256(k.gpart_bytes);
   }
   k.total = o;
