@@ -145,8 +145,26 @@ def run_path(H, torch, w, precision, steps, warmup, tol, timing, a):
                     torch.cuda.synchronize()
                     lat_g.append(time.perf_counter() - t0)
                 total_g = time.perf_counter() - t_g
+        # one DDM application without refinement (the method used once, as
+        # in one preconditioner call), on b = h^2 f on the interior nodes of
+        # the global grid (zero in the layer): `steps` calls timed
+        W = w["W"]
+        gshape = tuple(n + 2 * W for n in w["kappa"].shape)
+        b = torch.zeros((nrhs,) + gshape, dtype=torch.complex128, device=f.device)
+        b[(slice(None),) + tuple(slice(W, W + n) for n in w["kappa"].shape)] = w["h"] ** 2 * f
+        z = torch.empty_like(b)
+        for _ in range(2):
+            H.hdsw_apply_precond(ctx, b, z, nrhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            H.hdsw_apply_precond(ctx, b, z, nrhs)
+        torch.cuda.synchronize()
+        t_app = (time.perf_counter() - t0) / steps
+        del b
         fb, nops, ws = H.hdsw_query(ctx)
         return dict(tuning=dict(key=tkey, params=tuned["params"] if tuned else "built-in rules"),
+                    t_app=t_app, z_app=z,
                     total=total, lat=lat, info=info, x=x.cpu().numpy(), t_factor=t_factor,
                     lat_g=lat_g, total_g=total_g,
                     kt=kt, kt_all=kt_all, t_all_solve=t_all_solve, dom=dom,
@@ -346,6 +364,23 @@ def main():
     if fp64:
         x1, x2 = mixed["x"], fp64["x"]
         rel_mf = max(np.linalg.norm(p - q) / np.linalg.norm(q) for p, q in zip(x1, x2))
+    # one DDM application without refinement, per precision
+    one_app = {"mixed_rhs_per_s": round(nrhs / mixed["t_app"], 3),
+               "mixed_ms": round(mixed["t_app"] * 1e3, 3)}
+    if fp64:
+        zm, zf = mixed["z_app"], fp64["z_app"]
+        d = torch.linalg.vector_norm((zm - zf).reshape(nrhs, -1), dim=1)
+        nz = torch.linalg.vector_norm(zf.reshape(nrhs, -1), dim=1)
+        one_app.update(fp64_rhs_per_s=round(nrhs / fp64["t_app"], 3),
+                       fp64_ms=round(fp64["t_app"] * 1e3, 3),
+                       speedup_mixed_vs_fp64=round(fp64["t_app"] / mixed["t_app"], 3),
+                       rel_diff_mixed_vs_fp64=float((d / nz).max()))
+    one_app["note"] = ("one DDM application (rounds as configured) on b = h^2 f, no "
+                       "refinement; the FP64 application matches the oracle's step-by-step "
+                       "DDM to 1e-10 in the parity tests")
+    mixed.pop("z_app", None)
+    if fp64:
+        fp64.pop("z_app", None)
     # accuracy against the oracle's global solution: sampled values written
     # by tests/golden/make_samples.py (oracle only), when present
     err_glob = None
@@ -413,6 +448,7 @@ def main():
         "rel_residual_max": max(r for _, r in mixed["info"]),
         "rel_diff_mixed_vs_fp64": rel_mf,
         "rel_err_vs_oracle_global_sampled": err_glob,
+        "one_application": one_app,
         "factor_s": {"mixed": round(mixed["t_factor"], 3),
                      "fp64": round(fp64["t_factor"], 3) if fp64 else None},
         "roofline": roof, "kernels": kernels, "factor_mfma": factor_mfma(mixed, fp64),
