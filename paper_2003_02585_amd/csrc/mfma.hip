@@ -235,7 +235,11 @@ __device__ __forceinline__ cpx<T> prod_y(const cpx<T>* red, int nP, int rc) {
 // ------------------------------------------------------------ solve A
 // EPT epilogue elements per thread have their global operands prefetched
 // before the block product (EPT * threads >= 8 NG n is checked at launch).
-// A workgroup owns 8 NG columns of one batch entry and one chain.
+// A workgroup owns 8 NG columns of one batch entry and one chain.  Entry
+// idx of the epilogue is row idx / 8 NG, column idx % 8 NG: the lanes of a
+// wave read the partial sums and write the next vector at consecutive LDS
+// addresses (row-major [row][8 NG]), free of bank conflicts (with the row
+// fastest, the lanes of a wave would all meet in two banks).
 template <class T, int MAXT, int KSB, int NW, int EPT, int NG>
 __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict__ X,
                                                        size_t xstride,
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
-      int c = idx / n, r = idx - c * n;
+      int r = idx / NCOL, c = idx - r * NCOL;
       if (!(idx < NCOL * n && c < nc)) c = r = 0;   // unused value: the load stays unconditional
       fpre[q] = pb[((size_t)kn * C + c0 + c) * n + r];
       apre[q] = ay[(size_t)face * n + r];
@@ -293,7 +297,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
-      int c = idx / n, r = idx - c * n;
+      int r = idx / NCOL, c = idx - r * NCOL;
       if (idx < NCOL * n && c < nc) {
         cpx<T> y = prod_y<T, NW, NG>(red, nP, r * NCOL + c);
         pb[((size_t)k * C + c0 + c) * n + r] = y;
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
-      int c = idx / n, r = idx - c * n;
+      int r = idx / NCOL, c = idx - r * NCOL;
       if (!(idx < NCOL * n && c < nc)) r = 0;
       apre[q] = ay[(size_t)face * n + r];
     }
@@ -373,7 +377,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
-      int c = idx / n, r = idx - c * n;
+      int r = idx / NCOL, c = idx - r * NCOL;
       if (idx < NCOL * n && c < nc) {
         cpx<T> x = prod_y<T, NW, NG>(red, nP, r * NCOL + c);
         if (half == 0) pb[((size_t)mid * C + c0 + c) * n + r] = x;
@@ -393,7 +397,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
-      int c = idx / n, r = idx - c * n;
+      int r = idx / NCOL, c = idx - r * NCOL;
       if (!(idx < NCOL * n && c < nc)) c = r = 0;
       wpre[q] = pb[((size_t)k * C + c0 + c) * n + r];
       apre[q] = ay[(size_t)face * n + r];
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       int idx = tid + q * NT;
-      int c = idx / n, r = idx - c * n;
+      int r = idx / NCOL, c = idx - r * NCOL;
       if (idx < NCOL * n && c < nc) {
         cpx<T> x = wpre[q] - prod_y<T, NW, NG>(red, nP, r * NCOL + c);
         pb[((size_t)k * C + c0 + c) * n + r] = x;
