@@ -157,3 +157,61 @@ def test_kernel_timing_runs_eager_with_graphs_on(H):
     assert n == 6 and ms > 0
     for o in outs:
         assert np.array_equal(o, outs[0])
+
+
+def test_recording_beside_a_factorizing_thread(H):
+    # A worker thread sets up, factors and destroys contexts (allocations,
+    # frees, blocking copies) while the main thread keeps recording and
+    # replaying DDM applications of another context, each with new arrays
+    # (a new graph per pair).  Neither side may fail, and every replay
+    # equals the eager result of the same input bit for bit.
+    import threading
+    N, W, P = 64, 8, (4, 4)
+    h = 1.0 / N
+    kap = wl.constant_kappa((N, N), 2 * np.pi / (10 * h))
+    f = wl.sources((N, N), h, wl.random_positions(2, 2, 9, 4 * h, 1 - 4 * h), 2 * h)
+    prob = O.Problem(kap, h, W)
+    b = torch.from_numpy(np.stack([O.global_rhs(prob, fi) for fi in f])).cuda()
+    _say("graph recording beside a factorizing thread")
+    ref_ctx = _ctx(H, kap, h, P, W, precision=H.HDSW_MIXED, graphs=0)
+    ctx = _ctx(H, kap, h, P, W, precision=H.HDSW_MIXED, graphs=1)
+    errors, done, factored = [], threading.Event(), [0]
+
+    def worker():
+        try:
+            s = torch.cuda.Stream()
+            k2 = wl.two_layer_kappa((N, N), h, 2 * np.pi / (10 * h), 3 * np.pi / (10 * h), 0.53)
+            while not done.is_set():
+                c = H.hdsw_setup(k2, h, P, W, H.hdsw_default_options(precision=H.HDSW_MIXED),
+                                 stream=s.cuda_stream)
+                try:
+                    H.hdsw_factor(c)
+                    H.hdsw_batch_reserve(c, 2)
+                finally:
+                    H.hdsw_destroy(c)
+                factored[0] += 1
+        except Exception as e:      # reported by the main thread
+            errors.append(e)
+
+    t = threading.Thread(target=worker)
+    t.start()
+    try:
+        zref = torch.zeros_like(b)
+        H.hdsw_apply_precond(ref_ctx, b, zref, 2)
+        it = 0
+        while (it < 12 or factored[0] < 3) and it < 400 and not errors:
+            it += 1
+            r = b.clone()
+            z = torch.zeros_like(b)
+            for _ in range(3):               # eager, recorded, replayed
+                H.hdsw_apply_precond(ctx, r, z, 2)
+                torch.cuda.synchronize()
+                assert torch.equal(z, zref), it
+    finally:
+        done.set()
+        t.join()
+        H.hdsw_destroy(ctx)
+        H.hdsw_destroy(ref_ctx)
+    _say(f"  {it} recorded applications beside {factored[0]} factorizations")
+    assert not errors, errors
+    assert factored[0] >= 3
