@@ -1,14 +1,19 @@
-"""Second-order convergence of the GPU solve to the analytic radiating
-solution (Sec. 5.1, Table 1's setup: constant medium, k = 50 pi, 4 x 4
-subdomains, a smoothed point source at the centre of the unit square).
+"""Second-order convergence of the GPU solve, the experiments of Sec. 5.1.
 
-The mixed-precision GPU solve (complex64 DDM, FP64 refinement to a relative
-residual of 1e-10) is compared on three meshes with the free-space solution
-of eq. (helm) with the radiation condition for a unit-mass Gaussian source of
-fixed width s, u = -(i/4) exp(-k^2 s^2 / 2) H0^(1)(k r) (the paper's
-L G = -delta convention), in the annulus 0.2 < r < 0.42 away from source and
-layer.  The layer keeps a fixed physical depth (W = N / 24).  The observed
-rate between successive meshes must be at least 1.8 (the paper reports 2.0).
+Constant media (Table 1's 2D setup: k = 50 pi, 4 x 4 subdomains; the 3D
+one of Table 4 at half its frequency, 3 x 3 x 3): the mixed-precision GPU
+solve (complex64 DDM, FP64 refinement to a relative residual of 1e-10) is
+compared on three meshes with the free-space solution of eq. (helm) with
+the radiation condition for a unit-mass Gaussian source of fixed width s
+(2D: u = -(i/4) exp(-k^2 s^2 / 2) H0^(1)(k r), the paper's L G = -delta
+convention; 3D: -exp(i k r) / (4 pi r) exp(-k^2 s^2 / 2)), away from
+source and layer; the layer keeps a fixed physical depth.
+
+Two-layered media (Tables 2 and 3: one source, or four symmetric sources
+with the extra round), where no closed form exists: successive
+differences on meshes N, 3N, 9N with coinciding nodes.
+
+The observed rate must be at least 1.8 everywhere (the paper reports 2.0).
 """
 
 import sys
@@ -116,3 +121,58 @@ def test_3d_constant_medium_converges_at_second_order(H):
     _say(f"  rates {rates}")
     assert np.all(rates >= 1.8), (errs, rates)
     assert errs[-1] < 0.1
+
+
+def _smooth_two_layer(N, h, k_down, k_up, eta, eps):
+    # k(y): k_down below eta, k_up above eta + eps, linear in between
+    # (the profile of Sec. 5.1's two-layered example)
+    y = (np.arange(N) + 0.5) * h
+    w = np.clip((y - eta) / eps, 0.0, 1.0)
+    k = k_down * (1 - w) + k_up * w
+    return np.repeat(k[:, None], N, axis=1)
+
+
+@pytest.mark.parametrize("nsrc,rounds", [(1, 1), (4, 2)])
+def test_two_layer_tables_converge_at_second_order(H, nsrc, rounds):
+    # The two-layered example of Sec. 5.1 (Tables 2 and 3: k_down / k_up =
+    # 0.8, interface at 0.65 with a thin linear transition, 4 x 4 subdomains,
+    # one source, or four symmetric ones with the extra round), at a quarter
+    # of the paper's frequency so that three meshes fit the line-block path:
+    # k_down = 12.5 pi, k_up = 15.625 pi, transition 0.04 (four times the
+    # paper's width, as the wavelength).  No closed form exists, so the rate
+    # comes from successive differences on meshes N, 3N, 9N, whose
+    # cell-centred nodes coincide (node p of mesh N is node 3p + 1 of 3N):
+    # |u_N - u_3N| / |u_3N - u_9N| = 9 for second order.
+    k_down, k_up, eta, eps = 12.5 * np.pi, 15.625 * np.pi, 0.65, 0.04
+    s = 0.04
+    base = [(0.28, 0.27)]
+    if nsrc == 4:
+        base = [(0.28, 0.27), (0.72, 0.27), (0.28, 0.73), (0.72, 0.73)]
+    meshes = (48, 144, 432)
+    sols = []
+    for N in meshes:
+        h = 1.0 / N
+        W = N // 12               # the layer keeps its physical depth, 1/12
+        kap = _smooth_two_layer(N, h, k_down, k_up, eta, eps)
+        f = sum(wl.gaussian_source((N, N), h, p, s) for p in base)[None].astype(np.complex128)
+        _say(f"two-layer, {nsrc} source(s): N = {N}, W = {W}, 4 x 4, {rounds} round(s), mixed")
+        opt = H.hdsw_default_options(precision=H.HDSW_MIXED, rounds=rounds, tol=1e-10,
+                                     max_iter=60)
+        ctx = H.hdsw_setup(kap, h, (4, 4), W, opt,
+                           stream=torch.cuda.current_stream().cuda_stream)
+        try:
+            H.hdsw_factor(ctx)
+            ft = torch.from_numpy(f).cuda()
+            xt = torch.zeros_like(ft)
+            info, _ = H.hdsw_solve(ctx, ft, xt, 1)
+            sols.append(xt.cpu().numpy()[0])
+        finally:
+            H.hdsw_destroy(ctx)
+        _say(f"  {info[0][0]} iterations, residual {info[0][1]:.1e}")
+    d = []
+    for a, b in ((0, 1), (1, 2)):
+        fine = sols[b][1::3, 1::3]
+        d.append(np.linalg.norm(sols[a] - fine) / np.linalg.norm(fine))
+    rate = np.log(d[0] / d[1]) / np.log(3.0)
+    _say(f"  differences {d[0]:.3e} {d[1]:.3e}, rate {rate:.2f}")
+    assert rate >= 1.8, (d, rate)
