@@ -11,10 +11,17 @@ application (the extra round of Thm 3.10); FP64 refinement to
 ||b - S x|| / ||b|| <= tol.  --config c2d is the 1024^2 constant medium
 (8 x 8, 16 sources, one round), --config c3d the 96^3 one.
 
+tol (default 1e-8) is the residual threshold calibrated against the
+oracle's global solution so that the metric's relative error of 1e-8 holds
+with a wide margin: at tol = 1e-8 the sampled relative error is 3.0e-10 on
+the 2048^2 workload and 9.1e-11 on the 1024^2 one (6.5e-14 at 1e-10).
+The line reports the error it reaches.
+
 One step = one hdsw_solve of the whole batch (factors resident, sources
 resident in HBM).  value = nrhs * steps / timed seconds; p50/p99 over the
 timed solves.  The mixed result is checked against sampled values of the
-oracle's global solution (tests/golden/samples_<config>.npz) when present.
+oracle's global solution (tests/golden/samples_<config>.npz, or
+glob_c3d.npz for the 96^3 workload) when present.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -46,7 +53,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="layer2d",
                     choices=["small2d", "c2d", "layer2d", "c3d"])
-    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--tol", type=float, default=1e-8,
+                    help="relative residual threshold of both paths (calibrated: see above)")
     ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=None,
@@ -384,7 +392,8 @@ def main():
     # accuracy against the oracle's global solution: sampled values written
     # by tests/golden/make_samples.py (oracle only), when present
     err_glob = None
-    gpath = os.path.join(ROOT, "tests", "golden", f"samples_{a.config}.npz")
+    gname = "glob_c3d.npz" if a.config == "c3d" else f"samples_{a.config}.npz"
+    gpath = os.path.join(ROOT, "tests", "golden", gname)
     if os.path.exists(gpath) and a.rounds is None and not over:
         g = np.load(gpath)
         xs = mixed["x"].reshape(nrhs, -1)[:, g["index"]]
