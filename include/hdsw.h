@@ -35,7 +35,12 @@
  *    pointer) returns HDSW_EINVAL and leaves the context usable.
  *  - Every call is ordered on the context's stream and returns when its
  *    work is complete.  One host thread per context; separate contexts may
- *    be used concurrently on separate streams.
+ *    be used concurrently on separate streams and host threads.  The
+ *    library's runtime calls that may wait on other streams (allocation,
+ *    free, blocking copies, creation of streams, events and graphs) and its
+ *    recording of a DDM application as a graph hold one process-wide lock,
+ *    so one thread may factor a context while another records and replays
+ *    applications of a different one.
  *  - Nothing throws or aborts across this interface; every function that
  *    can fail returns an hdsw_status.  HDSW_EDEVICE is sticky: the context
  *    must be destroyed.
