@@ -804,13 +804,14 @@ __global__ void k_form_plane(cpx<T>* X, const cpx<T>* coefT, size_t cstride, Geo
 }
 
 // rbuf: 2 n 32 elements per distinct operator (panel rows R and columns E)
-// Two-level panels for blocks up to 2048 nodes: outer panels of OB = 64
+// Two-level panels for blocks up to 2048 nodes: outer panels of OB = 128
 // columns, each eliminated as inner panels of NBR columns in registers
 // (k_gj_panel_reg) whose updates reach only the outer panel's other
 // columns (k_gj_inner); the rest of the matrix then takes the outer panel's
-// moves and one rank-64 complex GEMM.  Larger blocks: 32-column panels
-// eliminated in global memory (k_gj_panel) and a rank-32 GEMM each.
-constexpr int kGjOuter = 64;
+// moves and one rank-128 complex GEMM (measured at 96^3 with 27 operators:
+// rank 64 1.78 s, 128 1.61 s, 256 1.66 s).  Larger blocks: 32-column
+// panels eliminated in global memory (k_gj_panel) and a rank-32 GEMM each.
+constexpr int kGjOuter = 128;
 template <class T>
 constexpr int gj_inner_nb() { return sizeof(T) == 4 ? 16 : 8; }
 static bool gj_two_level(int n) { return n <= 2048; }
