@@ -1387,14 +1387,19 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   cpx<T>* bp = reinterpret_cast<cpx<T>*>(smem_raw);        // [2 tiles][LMAX][kSweepRS] pairs
   const int NI = g.NI;
   // XCD-aware mapping: workgroups are dispatched round-robin over the 8
-  // XCDs, so ids with the same id % 8 share an L2.  All subdomains of one
-  // row tile get the same XCD, so its slice of T is fetched into that L2.
+  // XCDs (id % 8), each with its own L2.  The step's (row tile, subdomain)
+  // pairs, row tile major, are cut into 8 contiguous runs of equal length,
+  // one per XCD: every XCD gets the same work, and the subdomains of one
+  // row tile (which read the same slice of T when they share an operator)
+  // sit on at most two XCDs.
   const int nrt = (nout + RWS - 1) / RWS;
   const int cnt = sl.n;
-  const int xcd = blockIdx.x & 7, q8 = blockIdx.x >> 3;
-  const int rtile = xcd + 8 * (q8 / cnt);
-  if (rtile >= nrt) return;
-  const int s = sl.sub[q8 % cnt], op = sl.op[q8 % cnt];
+  const int np = nrt * cnt;
+  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int pair = xcd * np / 8 + loc;
+  if (pair >= (xcd + 1) * np / 8) return;
+  const int rtile = pair / cnt, si = pair - rtile * cnt;
+  const int s = sl.sub[si], op = sl.op[si];
   const int cg = blockIdx.y;                               // 16-column group
   const int c0 = cg * 16;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1861,7 +1866,7 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
       // LDS: the staged operand pairs, or the KH partial tiles of the sum
       size_t lds = std::max<size_t>((size_t)2 * LMAX * kSweepRS,
                                     (size_t)(8 / RW) * 16 * 16 * RW) * sizeof(cpx<T>);
-      dim3 grid(8 * ((nrt + 7) / 8) * sl.n, Cp / 16, 1);
+      dim3 grid(8 * ((nrt * sl.n + 7) / 8), Cp / 16, 1);
       hipLaunchKernelGGL((k_sweep_step<T, KB, RW>), grid, dim3(512), lds, c->stream,
                          (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_cface,
                          (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_y, sl, L, C, fin, fout, nout,
