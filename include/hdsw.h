@@ -260,6 +260,16 @@ hdsw_status hdsw_batch_take(hdsw_ctx* ctx, int slot, hdsw_c128* x_dev);
  *   gemm_skinny : 3D products with at most 8 columns per operator, 1 =
  *                 stream the matrix through the skinny kernel, 2 = tiled
  *                 kernel (order of the sum differs at the rounding level).
+ *   sweep_nw    : 2D sweep step, 8 waves per workgroup (one workgroup per
+ *                 CU, long face chunks staged at once) or 4 (two per CU,
+ *                 shorter chunks); with sweep_rw it sets how a sum is
+ *                 split in parts (results change at the rounding level).
+ *   sweep_sched : 2D sweep steps, 1 = one launch per step in sweep order,
+ *                 2 = the steps of one level of the slot dependences (a
+ *                 subdomain's sweep after every trace its slot receives and
+ *                 after its previous sweep) share a launch; every slot
+ *                 still receives its additions in sweep order, so results
+ *                 do not change.
  * hdsw_tuning_set validates every field (EINVAL for values outside the
  * lists above) and drops captured graphs; hdsw_tuning_get returns the
  * fields as set. */
@@ -268,6 +278,8 @@ typedef struct {
   int sweep_rw;
   int sweep_kb;
   int gemm_skinny;
+  int sweep_nw;
+  int sweep_sched;
 } hdsw_tuning;
 hdsw_status hdsw_tuning_set(hdsw_ctx* ctx, const hdsw_tuning* t);
 hdsw_status hdsw_tuning_get(const hdsw_ctx* ctx, hdsw_tuning* t);

@@ -46,9 +46,15 @@ def candidates(dim, mixed):
     if dim == 2:
         ngs = (1, 2) if mixed else (1,)
         kbs = (6, 8, 10) if mixed else (3, 4, 5, 6)
-        return [dict(solve_ng=ng, sweep_rw=rw, sweep_kb=kb, gemm_skinny=0)
-                for ng, rw, kb in itertools.product(ngs, (2, 4), kbs)]
-    return [dict(solve_ng=0, sweep_rw=0, sweep_kb=0, gemm_skinny=s) for s in (1, 2)]
+        # complex128 four-wave workgroups with four row tiles need more than
+        # half the register file at depths 5 and 6 (one workgroup per CU):
+        # left out
+        return [dict(solve_ng=ng, sweep_rw=rw, sweep_kb=kb, gemm_skinny=0, sweep_nw=nw,
+                     sweep_sched=0)
+                for ng, rw, kb, nw in itertools.product(ngs, (2, 4), kbs, (8, 4))
+                if mixed or not (nw == 4 and rw == 4 and kb >= 5)]
+    return [dict(solve_ng=0, sweep_rw=0, sweep_kb=0, gemm_skinny=s, sweep_nw=0, sweep_sched=0)
+            for s in (1, 2)]
 
 
 def time_application(H, torch, ctx, r, z, reps):
@@ -84,7 +90,8 @@ def search(H, torch, ctx, r, dim, mixed, reps=5, log=None):
             log(f"  {cand}: {ms:.3f} ms")
     best, best_ms = min(rows, key=lambda t: t[1])
     if best_ms >= default_ms:
-        best, best_ms = dict(solve_ng=0, sweep_rw=0, sweep_kb=0, gemm_skinny=0), default_ms
+        best, best_ms = dict(solve_ng=0, sweep_rw=0, sweep_kb=0, gemm_skinny=0,
+                             sweep_nw=0, sweep_sched=0), default_ms
     H.hdsw_tuning_set(ctx, **best)
     return dict(params=best, ms=best_ms, default_ms=default_ms, columns=int(r.shape[0]),
                 candidates=[[c, round(m, 4)] for c, m in rows])

@@ -205,6 +205,8 @@ hdsw_status hdsw_tuning_set(hdsw_ctx* ctx, const hdsw_tuning* t) {
   p.sweep_rw = t->sweep_rw;
   p.sweep_kb = t->sweep_kb;
   p.gemm_skinny = t->gemm_skinny;
+  p.sweep_nw = t->sweep_nw;
+  p.sweep_sched = t->sweep_sched;
   try {
     return hdsw::tuning_set(ctx, p);
   } catch (...) {
@@ -218,6 +220,8 @@ hdsw_status hdsw_tuning_get(const hdsw_ctx* ctx, hdsw_tuning* t) {
   t->sweep_rw = ctx->tune.sweep_rw;
   t->sweep_kb = ctx->tune.sweep_kb;
   t->gemm_skinny = ctx->tune.gemm_skinny;
+  t->sweep_nw = ctx->tune.sweep_nw;
+  t->sweep_sched = ctx->tune.sweep_sched;
   return HDSW_OK;
 }
 

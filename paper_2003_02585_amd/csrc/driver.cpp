@@ -66,6 +66,58 @@ static bool opposite_blocked(const int* e, const int* dg, const int* du, int dim
   return false;
 }
 
+// Levels of the sweep steps in the routing dependences.  Subdomain s in
+// sweep L reads its slot L, which every neighbour s' fills across the shared
+// face in each sweep L' <= L that routes that face to L (L' = L: the
+// neighbour's earlier step of the same sweep); and it adds into the slots
+// of its neighbours, which the same neighbour-sweep pairs also add into.
+// Taking (L, s) after all of those writers and after (L - 1, s) orders
+// every slot's additions by sweep, as the step-by-step order does, so the
+// results do not change.  level(L, s) = 1 + the largest level of those
+// predecessors; the steps whose subdomains share a level go to one launch
+// (at most two steps of consecutive sweeps on the partitions tried).  A step
+// whose subdomains would land on several levels is not merged.
+static void build_levels(const Geometry& g, Schedule& s) {
+  s.lfirst.clear();
+  s.lsteps.clear();
+  const int nst = s.nsweeps * s.nsteps;
+  std::vector<int> lev((size_t)s.nsweeps * g.nsub, 0), slev(nst, -1);
+  bool uniform = g.dim == 2;
+  for (int L = 0; L < s.nsweeps && uniform; ++L)
+    for (int st = 0; st < s.nsteps && uniform; ++st) {
+      const int off = s.step_off[L * s.nsteps + st], cnt = s.step_cnt[L * s.nsteps + st];
+      for (int i = 0; i < cnt; ++i) {
+        const int sub = s.step_subs[off + i];
+        int cc[3], v = L > 0 ? lev[(size_t)(L - 1) * g.nsub + sub] + 1 : 0;
+        g.sub_coords(sub, cc);
+        for (int f = 0; f < 2 * g.dim; ++f) {
+          int nc[3] = {cc[0], cc[1], cc[2]};
+          nc[f >> 1] += (f & 1) ? 1 : -1;
+          if (nc[f >> 1] < 0 || nc[f >> 1] >= g.P[f >> 1]) continue;
+          const int nb = g.sub_id(nc);
+          for (int L0 = 0; L0 <= L; ++L0)   // the neighbour sends across face f ^ 1
+            if (s.lprime[L0 * 6 + (f ^ 1)] == L)
+              v = std::max(v, lev[(size_t)L0 * g.nsub + nb] + 1);
+        }
+        lev[(size_t)L * g.nsub + sub] = v;
+        if (i == 0) slev[L * s.nsteps + st] = v;
+        else if (slev[L * s.nsteps + st] != v) uniform = false;
+      }
+    }
+  if (!uniform) return;          // one launch per step
+  int nlev = 0;
+  for (int v : slev) nlev = std::max(nlev, v + 1);
+  std::vector<std::vector<int>> by(nlev);
+  for (int i = 0; i < nst; ++i)
+    if (slev[i] >= 0) by[slev[i]].push_back(i);
+  for (auto& v : by) {
+    if (v.empty()) continue;
+    s.lfirst.push_back((int)s.lsteps.size());
+    s.lsteps.insert(s.lsteps.end(), v.begin(), v.end());
+  }
+  s.lfirst.push_back((int)s.lsteps.size());
+}
+
 static void build_schedule(hdsw_ctx* c) {
   Geometry& g = c->g;
   Schedule& s = c->sch;
@@ -117,6 +169,7 @@ static void build_schedule(hdsw_ctx* c) {
       int lq = s.lprime[L0 * 6 + f];
       if (lq >= 0) s.in_active[lq * 6 + (f ^ 1)] = 1;
     }
+  build_levels(g, s);
 }
 
 // ------------------------------------------------------------ PML profile
@@ -856,22 +909,27 @@ static hdsw_status ddm_impl(hdsw_ctx* c, const c128* r, c128* out, int C, int ac
   HCHK(launch_extract_iface<T>(c, g.nsub, C, c->d_y, (long long)C * g.NI, g.NI));
   size_t iface = (size_t)g.nsub * C * g.NI * e;
   HCHK(launch_zero(c, c->d_slots, iface * s.nsweeps));
-  for (int L = 0; L < s.nsweeps; ++L) {
-    for (int st = 0; st < s.nsteps; ++st) {
-      int off = s.step_off[L * s.nsteps + st], cnt = s.step_cnt[L * s.nsteps + st];
-      if (cnt == 0) continue;
-      {
-        double nin = 0, nout = 0;
-        for (int f = 0; f < 2 * g.dim; ++f) {
-          if (s.in_active[L * 6 + f]) nin += 2 * g.side_len[f];
-          if (s.lprime[L * 6 + f] >= 0) nout += 2 * g.side_len[f];
-        }
-        double fl = 8.0 * nin * nout * C * cnt;
-        double by = nin * nout * e * std::min(cnt, c->nops) + (nin + 2 * nout) * C * e * cnt;
-        TimedScope ts(c, KT_GEMM, fl, by);
-        HCHK(launch_sweep_step<T>(c, L, st, off, cnt, C));
+  // the steps in sweep order, or (2D) the steps of one level of the slot
+  // dependences per launch; both orders give the same results
+  const bool merged = !s.lfirst.empty() && c->tune.sweep_sched != 1;
+  const int nlaunch = merged ? (int)s.lfirst.size() - 1 : s.nsweeps * s.nsteps;
+  for (int i = 0; i < nlaunch; ++i) {
+    const int* sidx = merged ? &s.lsteps[s.lfirst[i]] : &i;
+    const int nst = merged ? s.lfirst[i + 1] - s.lfirst[i] : 1;
+    double fl = 0, by = 0;
+    for (int k = 0; k < nst; ++k) {
+      const int L = sidx[k] / s.nsteps, cnt = s.step_cnt[sidx[k]];
+      double nin = 0, nout = 0;
+      for (int f = 0; f < 2 * g.dim; ++f) {
+        if (s.in_active[L * 6 + f]) nin += 2 * g.side_len[f];
+        if (s.lprime[L * 6 + f] >= 0) nout += 2 * g.side_len[f];
       }
+      fl += 8.0 * nin * nout * C * cnt;
+      by += nin * nout * e * std::min(cnt, c->nops) + (nin + 2 * nout) * C * e * cnt;
     }
+    if (fl == 0 && by == 0) continue;    // empty steps
+    TimedScope ts(c, KT_GEMM, fl, by);
+    HCHK(launch_sweep_steps<T>(c, sidx, nst, C));
   }
   HCHK(launch_fill_panel<T>(c, 1, g.nsub, c->d_all_subs, C, r, 0));
   {
@@ -1267,7 +1325,8 @@ hdsw_status tuning_set(hdsw_ctx* c, const TuneParams& t) {
   };
   if (!in(t.solve_ng, {0, 1, 2}) || !in(t.sweep_rw, {0, 2, 4}) ||
       !(c64 ? in(t.sweep_kb, {0, 6, 8, 10}) : in(t.sweep_kb, {0, 3, 4, 5, 6})) ||
-      !in(t.gemm_skinny, {0, 1, 2}))
+      !in(t.gemm_skinny, {0, 1, 2}) || !in(t.sweep_nw, {0, 4, 8}) ||
+      !in(t.sweep_sched, {0, 1, 2}))
     return HDSW_EINVAL;
   graphs_clear(c);   // captured launches hold the old parameters
   c->tune = t;

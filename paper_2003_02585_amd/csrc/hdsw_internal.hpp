@@ -152,6 +152,10 @@ struct Schedule {
   // in_active[L * 6 + face] = 1 if the face can hold a received trace in
   // sweep L (some sweep L0 <= L routes a trace across it into slot L)
   std::vector<int> in_active;
+  // Steps by level of the routing dependences (2D): launch i may run the
+  // steps lsteps[lfirst[i] .. lfirst[i + 1]) (indices L * nsteps + st)
+  // together, since none of them writes a slot another one reads or writes
+  std::vector<int> lfirst, lsteps;
 };
 
 // ---------------------------------------------------------------- buffers
@@ -167,6 +171,9 @@ struct TuneParams {
   int sweep_kb = 0;     // 2D sweep step: slices of T per register batch
                         // (complex64 6/8/10, complex128 3/4/5/6)
   int gemm_skinny = 0;  // 3D products with <= 8 columns: 1 streaming, 2 tiled
+  int sweep_nw = 0;     // 2D sweep step: 4 or 8 waves per workgroup
+  int sweep_sched = 0;  // 2D sweep steps: 1 one launch per step, 2 (rule)
+                        // the steps of one level of the routing dependences
 };
 
 struct Timing {
@@ -355,7 +362,7 @@ hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
 template <class T>
 hipError_t launch_write_owned(hdsw_ctx* c, int C, c128* glob, int accumulate);
 template <class T>
-hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C);
+hipError_t launch_sweep_steps(hdsw_ctx* c, const int* sidx, int nst, int C);
 template <class T>
 hipError_t launch_face_coef(hdsw_ctx* c);
 template <class T>

@@ -1308,9 +1308,18 @@ struct FaceSet {
 // 16 x 16 partitions of the benchmarks take one per step; 32 x 32 ones, in
 // the tests, two on their longer steps).
 constexpr int kStepListMax = 16;
-struct StepList {
-  int n;
-  int sub[kStepListMax], op[kStepListMax];
+// One or two steps of one launch (steps that no slot dependence orders, in
+// different sweeps): each a group with its own faces, chunking and
+// subdomains sub[first .. first + n)
+constexpr int kStepGroups = 2;
+struct StepGroup {
+  int L, nout, add_y, LMAX, nsub_chunks, first, n;
+  FaceSet fin, fout;
+};
+struct StepLaunch {
+  int ng;
+  StepGroup g[kStepGroups];
+  int sub[kStepGroups * kStepListMax], op[kStepGroups * kStepListMax];
 };
 __device__ inline int fs_find(const FaceSet& fs, int idx) {
   // the last active face that starts at or before idx (starts increase)
@@ -1356,12 +1365,16 @@ __device__ inline StepOut step_out(const GeoDev& g, const FaceSet& fout, int s, 
   return o;
 }
 
-// Longest face chunk of the sum staged in LDS at once (a multiple of 4):
-// 2 tiles x lcap rows of kSweepRS operand pairs = 136 KB.  Rows hold 16
-// pairs and one of padding, so that the staging stores (one row per lane)
-// and the operand reads (four rows per wave) are free of bank conflicts.
-template <class T>
-__host__ __device__ constexpr int sweep_lcap() { return sizeof(T) == 4 ? 512 : 256; }
+// Longest face chunk of the sum staged in LDS at once (a multiple of 64):
+// 2 tiles x lcap rows of kSweepRS operand pairs, 136 KB for eight-wave
+// workgroups (one per CU), at most 80 KB for four-wave workgroups (two per
+// CU).  Rows hold 16 pairs and one of padding, so that the staging stores
+// (one row per lane) and the operand reads (four rows per wave) are free of
+// bank conflicts.
+template <class T, int NWV>
+__host__ __device__ constexpr int sweep_lcap() {
+  return NWV == 8 ? (sizeof(T) == 4 ? 512 : 256) : (sizeof(T) == 4 ? 256 : 128);
+}
 constexpr int kSweepRS = 17;
 // Two-tile workgroups per 16-column group of a step above which the
 // four-tile form is used (the 1024^2 workload's largest steps, 8 subdomains
@@ -1375,31 +1388,38 @@ constexpr int kSweepRows = 320;
 // pair per 4-deep slice.  Four accumulators (two tiles x real/imaginary part
 // of X) keep dependent MFMAs apart; the T columns of a face are contiguous,
 // so its operand is walked by pointer increments.
-template <class T, int KB, int RW>
-__global__ __launch_bounds__(512) void k_sweep_step(
+template <class T, int KB, int RW, int NWV>
+__global__ __launch_bounds__(NWV * 64) void k_sweep_step(
     const cpx<T>* __restrict__ Tm, const cpx<T>* __restrict__ cface, cpx<T>* slots,
-    const cpx<T>* __restrict__ ybuf, StepList sl, int L, int C, FaceSet fin, FaceSet fout,
-    int nout, int add_y, int LMAX, int nsub_chunks, GeoDev g) {
+    const cpx<T>* __restrict__ ybuf, StepLaunch sl, int C, GeoDev g) {
   typedef typename MF<T>::v4 v4;
-  // RW 16-row tiles per workgroup; the 8 waves split the sum in KH parts
-  constexpr int KH = 8 / RW, RWS = 16 * RW, NQ = (RWS * 16 + 511) / 512;
+  // RW 16-row tiles per workgroup; the NWV waves split the sum in KH parts
+  static_assert(NWV % RW == 0 && 8 % NWV == 0, "waves and row tiles");
+  constexpr int NT = NWV * 64;
+  constexpr int KH = NWV / RW, RWS = 16 * RW, NQ = (RWS * 16 + NT - 1) / NT;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* bp = reinterpret_cast<cpx<T>*>(smem_raw);        // [2 tiles][LMAX][kSweepRS] pairs
   const int NI = g.NI;
   // XCD-aware mapping: workgroups are dispatched round-robin over the 8
-  // XCDs (id % 8), each with its own L2.  The step's (row tile, subdomain)
-  // pairs, row tile major, are cut into 8 contiguous runs of equal length,
-  // one per XCD: every XCD gets the same work, and the subdomains of one
-  // row tile (which read the same slice of T when they share an operator)
-  // sit on at most two XCDs.
-  const int nrt = (nout + RWS - 1) / RWS;
-  const int cnt = sl.n;
-  const int np = nrt * cnt;
+  // XCDs (id % 8), each with its own L2.  The (row tile, subdomain) pairs
+  // of the launch, group by group and row tile major, are cut into 8
+  // contiguous runs of equal length, one per XCD: every XCD gets the same
+  // number of tiles, and the subdomains of one row tile (which read the
+  // same slice of T when they share an operator) sit on at most two XCDs.
+  const int np0 = (sl.g[0].nout + RWS - 1) / RWS * sl.g[0].n;
+  const int np = np0 + (sl.ng > 1 ? (sl.g[1].nout + RWS - 1) / RWS * sl.g[1].n : 0);
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
   const int pair = xcd * np / 8 + loc;
   if (pair >= (xcd + 1) * np / 8) return;
-  const int rtile = pair / cnt, si = pair - rtile * cnt;
-  const int s = sl.sub[si], op = sl.op[si];
+  const int gi = pair >= np0 ? 1 : 0;
+  const StepGroup& G = sl.g[gi];
+  const int L = G.L, nout = G.nout, add_y = G.add_y, LMAX = G.LMAX;
+  const int nsub_chunks = G.nsub_chunks, cnt = G.n;
+  const FaceSet& fin = G.fin;
+  const FaceSet& fout = G.fout;
+  const int lp = pair - (gi ? np0 : 0);
+  const int rtile = lp / cnt, si = lp - rtile * cnt;
+  const int s = sl.sub[G.first + si], op = sl.op[G.first + si];
   const int cg = blockIdx.y;                               // 16-column group
   const int c0 = cg * 16;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1412,23 +1432,28 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   // The B operand, g = [S_r, chi_r] v~ of the pairs received in slot L
   // (g[layer 1] = c pair[layer 0], g[layer 0] = -c pair[layer 1], c the
   // receiver's face coefficient), is formed while it is staged in LDS, one
-  // face chunk at a time.  Each thread holds its share of a chunk (2 tiles
-  // x 4 nks x 8 values, at most SJ per thread) in registers: the loads of
-  // the next chunk are issued before the current chunk's sum.
-  // Wave w stages column w of both 8-column tiles, lane l the sum indices
-  // k = l + 64 i: the loads of a wave read 64 consecutive sources of one
-  // column.  SK blocks of 64 indices cover the longest chunk.
-  constexpr int SK = sweep_lcap<T>() / 64;
-  cpx<T> sv[2 * SK], cv[SK];
+  // face chunk at a time.  Each thread holds its share of a chunk in
+  // registers: the loads of the next chunk are issued before the current
+  // chunk's sum.  Wave w stages columns w + NWV j (j < CPW) of both
+  // 8-column tiles, lane l the sum indices k = l + 64 i: the loads of a
+  // wave read 64 consecutive sources of one column.  SK blocks of 64
+  // indices cover the longest chunk.
+  constexpr int SK = sweep_lcap<T, NWV>() / 64, CPW = 8 / NWV;
+  cpx<T> sv[2 * CPW * SK], cv[SK];
   const int nqc = fin.n * nsub_chunks;
   auto chunk_len = [&](int q) {                // sum length of chunk q (0: none)
     const int qf = q / nsub_chunks, sc = q - qf * nsub_chunks;
     return max(0, min(LMAX, 2 * pick(g.side_len, pick(fin.face, qf)) - sc * LMAX));
   };
-  const int scol0 = 2 * cg * 8 + wave, scol1 = scol0 + 8;   // tile 0 / tile 1 column
-  const bool ok0 = scol0 < C, ok1 = scol1 < C;
-  const cpx<T>* rcol0 = recv + (size_t)(ok0 ? scol0 : 0) * NI;
-  const cpx<T>* rcol1 = recv + (size_t)(ok1 ? scol1 : 0) * NI;
+  // staged column j of tile t: c0 + 8 t + wave + NWV j
+  bool sok[2 * CPW];
+  const cpx<T>* rcol[2 * CPW];
+#pragma unroll
+  for (int j = 0; j < 2 * CPW; ++j) {
+    const int col = c0 + 8 * (j & 1) + wave + NWV * (j >> 1);
+    sok[j] = col < C;
+    rcol[j] = recv + (size_t)(sok[j] ? col : 0) * NI;
+  }
   cpx<T>* lds_st = bp + (size_t)lane * kSweepRS + wave;
   auto stage_load = [&](int q) {
     const int qf = q / nsub_chunks, sc = q - qf * nsub_chunks;
@@ -1443,8 +1468,8 @@ __global__ __launch_bounds__(512) void k_sweep_step(
       const int kf = kb + (k < kn ? k : 0);    // index within the face's 2 len sources
       const bool lay1 = kf >= len;
       const int partner = so + kf + (lay1 ? -len : len);   // the pair's other layer
-      sv[2 * i] = rcol0[partner];
-      sv[2 * i + 1] = rcol1[partner];
+#pragma unroll
+      for (int j = 0; j < 2 * CPW; ++j) sv[2 * CPW * i + j] = rcol[j][partner];
       cv[i] = cf_op[so / 2 + kf - (lay1 ? len : 0)];
     }
   };
@@ -1457,11 +1482,12 @@ __global__ __launch_bounds__(512) void k_sweep_step(
       const int k = lane + 64 * i;
       if (k < k4) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          cpx<T> gv = cv[i] * sv[2 * i + t];
+        for (int j = 0; j < 2 * CPW; ++j) {
+          const int t = j & 1;
+          cpx<T> gv = cv[i] * sv[2 * CPW * i + j];
           if (kb + k < len) gv = -gv;          // layer 0 receives -c pair[layer 1]
-          if (!(k < kn && (t ? ok1 : ok0))) gv = mk<T>(T(0), T(0));
-          cpx<T>* row = lds_st + ((size_t)t * LMAX + 64 * i) * kSweepRS;
+          if (!(k < kn && sok[j])) gv = mk<T>(T(0), T(0));
+          cpx<T>* row = lds_st + ((size_t)t * LMAX + 64 * i) * kSweepRS + NWV * (j >> 1);
           row[0] = mk<T>(gv.re, -gv.im);
           row[8] = mk<T>(gv.im, gv.re);
         }
@@ -1551,7 +1577,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
   cpx<T> ey[NQ], ein[NQ], edst[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    int idx = tid + q * 512;
+    int idx = tid + q * NT;
     int col = idx / RWS, r = idx % RWS;
     int orow = rtile * RWS + r;
     eo[q] = StepOut{-1, -1, -1};
@@ -1617,7 +1643,7 @@ __global__ __launch_bounds__(512) void k_sweep_step(
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     if (eo[q].dst < 0) continue;
-    int idx = tid + q * 512;
+    int idx = tid + q * NT;
     int col = idx / RWS, r = idx % RWS;
     cpx<T> v = bp[col * RWS + r] + ey[q];
     slots[eo[q].dst] = edst[q] + (v - ein[q]);
@@ -1730,18 +1756,21 @@ hipError_t launch_face_coef(hdsw_ctx* c) {
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C) {
+// Active faces of sweep L: inputs are the faces that can hold a received
+// trace, outputs the faces whose trace some sweep uses (Rules 2.4/2.5,
+// 4.1/4.2); returns the output rows, nin the input sum length.
+static int step_faces(const hdsw_ctx* c, int L, FaceSet& fin, FaceSet& fout, int* nin) {
   const Geometry& g = c->g;
-  FaceSet fin{}, fout{};
-  int nin = 0, nout = 0;
+  fin = FaceSet{};
+  fout = FaceSet{};
+  int ni = 0, nout = 0;
   for (int f = 0; f < 2 * g.dim; ++f) {
     if (c->sch.in_active[L * 6 + f]) {
       fin.face[fin.n] = f;
-      fin.start[fin.n] = nin;
+      fin.start[fin.n] = ni;
       fin.lq[fin.n] = -1;
       fin.n++;
-      nin += 2 * g.side_len[f];
+      ni += 2 * g.side_len[f];
     }
     int lq = c->sch.lprime[L * 6 + f];
     if (lq >= 0) {
@@ -1752,90 +1781,152 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
       nout += 2 * g.side_len[f];
     }
   }
+  *nin = ni;
+  return nout;
+}
+
+template <class T>
+static hipError_t launch_sweep_step3(hdsw_ctx* c, int L, int st, int off, int cnt, int C) {
+  const Geometry& g = c->g;
+  FaceSet fin{}, fout{};
+  int nin = 0;
+  const int nout = step_faces(c, L, fin, fout, &nin);
   if (nout == 0) return hipSuccess;
-  if (g.dim == 3) {
-    const int* subs = c->d_step_subs + off;
-    // input faces in the padded k space of the tiled T
-    const int tk = c->t_tk;
-    FaceSet finp = fin;
-    int ninp = 0;
-    for (int q = 0; q < fin.n && nin > 0; ++q) {
-      finp.start[q] = ninp;
-      ninp += (2 * g.side_len[fin.face[q]] + tk - 1) / tk * tk;
-    }
-    if (nin > 0) {
-      long long tot = (long long)cnt * C * ninp;
-      int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
-      hipLaunchKernelGGL(k_trace_src_plain<T>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const cpx<T>*)c->d_cface, (const cpx<T>*)c->d_slots,
-                         (cpx<T>*)c->d_g, c->d_op_of_sub, subs, cnt, L, C,
-                         finp, ninp, c->gd);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    const int sidx = L * c->sch.nsteps + st;
-    GemmArgs a{};
-    a.M = c->tm_mpad[L];
-    a.N = 0;
-    a.Kd = ninp;
-    a.A = c->d_T;
-    a.lda = 0;
-    a.sAz = (long long)c->t_nrt * 64 * (long long)c->t_nkt * tk;
-    a.a_rt = c->d_tmap + c->tm_rt_off[L];
-    a.a_kt = c->d_tmap + c->tm_kt_off[L];
-    a.a_tile_ld = c->t_nkt;
-    a.c_row = c->d_tmap + c->tm_row_off[L];
-    a.B = c->d_g;
-    a.ldb = ninp;
-    a.sb = (long long)C * ninp;
-    a.sBz = 0;
-    a.C = c->d_out;
-    a.ldc = nout;
-    a.sc = (long long)C * nout;
-    a.sCz = 0;
-    a.cpb = C;
-    a.ids = c->d_sg_ids;
-    a.grp_op = c->d_sg_op + c->sg_first[sidx];
-    a.grp_off = c->d_sg_off + c->sg_first[sidx];
-    a.grp_cnt = c->d_sg_cnt + c->sg_first[sidx];
-    a.neg = 0;
-    a.beta = 0;
-    if (nin == 0) {
-      // nothing received yet: the outputs are the source-driven part alone
-      hipError_t e = launch_zero(c, c->d_out, (size_t)cnt * C * nout * sizeof(cpx<T>));
-      if (e != hipSuccess) return e;
-    } else {
-      if (tk != gemm_bk<T>()) return hipErrorInvalidValue;
-      a.no_skinny = c->tune.gemm_skinny == 2;
-      // fewer row tiles than the CUs hold workgroups (four each): split the
-      // sum, from the step's shape only (rows and operator groups); the
-      // streaming kernel of narrow products keeps one part
-      const int maxcols = c->sg_maxcnt[sidx] * C;
-      const bool skinny = maxcols <= 8 && !a.no_skinny;
-      const long long rtiles = (long long)(a.M / 64) * c->sg_n[sidx];
-      int ks = skinny ? 1 : (int)std::min<long long>(4, std::max<long long>(1, (1024 + rtiles - 1) / rtiles));
-      while (ks > 1 && (size_t)ks * c->sg_n[sidx] * maxcols * a.M * sizeof(cpx<T>) > c->gpart_bytes)
-        --ks;
-      a.ksplit = ks;
-      a.part = c->d_gpart;
-      hipError_t e = gemm<T>(c->stream, a, maxcols, c->sg_n[sidx]);
-      if (e != hipSuccess) return e;
-    }
-    long long tot = (long long)cnt * C * nout;
+  const int* subs = c->d_step_subs + off;
+  // input faces in the padded k space of the tiled T
+  const int tk = c->t_tk;
+  FaceSet finp = fin;
+  int ninp = 0;
+  for (int q = 0; q < fin.n && nin > 0; ++q) {
+    finp.start[q] = ninp;
+    ninp += (2 * g.side_len[fin.face[q]] + tk - 1) / tk * tk;
+  }
+  if (nin > 0) {
+    long long tot = (long long)cnt * C * ninp;
     int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(k_step_scatter<T>, dim3(blocks), dim3(256), 0, c->stream,
-                       (const cpx<T>*)c->d_out, (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_y, subs,
-                       cnt, L, C, fout, nout, L == 0 ? 1 : 0, c->gd);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_trace_src_plain<T>, dim3(blocks), dim3(256), 0, c->stream,
+                       (const cpx<T>*)c->d_cface, (const cpx<T>*)c->d_slots,
+                       (cpx<T>*)c->d_g, c->d_op_of_sub, subs, cnt, L, C,
+                       finp, ninp, c->gd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int sidx = L * c->sch.nsteps + st;
+  GemmArgs a{};
+  a.M = c->tm_mpad[L];
+  a.N = 0;
+  a.Kd = ninp;
+  a.A = c->d_T;
+  a.lda = 0;
+  a.sAz = (long long)c->t_nrt * 64 * (long long)c->t_nkt * tk;
+  a.a_rt = c->d_tmap + c->tm_rt_off[L];
+  a.a_kt = c->d_tmap + c->tm_kt_off[L];
+  a.a_tile_ld = c->t_nkt;
+  a.c_row = c->d_tmap + c->tm_row_off[L];
+  a.B = c->d_g;
+  a.ldb = ninp;
+  a.sb = (long long)C * ninp;
+  a.sBz = 0;
+  a.C = c->d_out;
+  a.ldc = nout;
+  a.sc = (long long)C * nout;
+  a.sCz = 0;
+  a.cpb = C;
+  a.ids = c->d_sg_ids;
+  a.grp_op = c->d_sg_op + c->sg_first[sidx];
+  a.grp_off = c->d_sg_off + c->sg_first[sidx];
+  a.grp_cnt = c->d_sg_cnt + c->sg_first[sidx];
+  a.neg = 0;
+  a.beta = 0;
+  if (nin == 0) {
+    // nothing received yet: the outputs are the source-driven part alone
+    hipError_t e = launch_zero(c, c->d_out, (size_t)cnt * C * nout * sizeof(cpx<T>));
+    if (e != hipSuccess) return e;
+  } else {
+    if (tk != gemm_bk<T>()) return hipErrorInvalidValue;
+    a.no_skinny = c->tune.gemm_skinny == 2;
+    // fewer row tiles than the CUs hold workgroups (four each): split the
+    // sum, from the step's shape only (rows and operator groups); the
+    // streaming kernel of narrow products keeps one part
+    const int maxcols = c->sg_maxcnt[sidx] * C;
+    const bool skinny = maxcols <= 8 && !a.no_skinny;
+    const long long rtiles = (long long)(a.M / 64) * c->sg_n[sidx];
+    int ks = skinny ? 1 : (int)std::min<long long>(4, std::max<long long>(1, (1024 + rtiles - 1) / rtiles));
+    while (ks > 1 && (size_t)ks * c->sg_n[sidx] * maxcols * a.M * sizeof(cpx<T>) > c->gpart_bytes)
+      --ks;
+    a.ksplit = ks;
+    a.part = c->d_gpart;
+    hipError_t e = gemm<T>(c->stream, a, maxcols, c->sg_n[sidx]);
+    if (e != hipSuccess) return e;
+  }
+  long long tot = (long long)cnt * C * nout;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_step_scatter<T>, dim3(blocks), dim3(256), 0, c->stream,
+                     (const cpx<T>*)c->d_out, (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_y, subs,
+                     cnt, L, C, fout, nout, L == 0 ? 1 : 0, c->gd);
+  return hipGetLastError();
+}
+
+// Sweep steps sidx[0 .. nst) (indices L * nsteps + st) that no slot
+// dependence orders: in 2D one launch of k_sweep_step takes up to two of
+// them (or two groups of kStepListMax subdomains of one step); 3D steps run
+// one after another.
+template <class T>
+hipError_t launch_sweep_steps(hdsw_ctx* c, const int* sidx, int nst, int C) {
+  const Geometry& g = c->g;
+  const Schedule& sc = c->sch;
+  if (g.dim == 3) {
+    for (int i = 0; i < nst; ++i) {
+      const int cnt = sc.step_cnt[sidx[i]];
+      if (cnt == 0) continue;
+      hipError_t e = launch_sweep_step3<T>(c, sidx[i] / sc.nsteps, sidx[i] % sc.nsteps,
+                                           sc.step_off[sidx[i]], cnt, C);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   const int Cp = (C + 15) / 16 * 16;
-  // LDS chunks of one input face (or a part of it): 2 tiles x LMAX rows of
-  // kSweepRS operand pairs, LMAX a multiple of 4 no larger than sweep_lcap
-  int flen = 0;
-  for (int q = 0; q < fin.n; ++q) flen = std::max(flen, 2 * g.side_len[fin.face[q]]);
-  const int lcap = sweep_lcap<T>();
-  const int nsub_chunks = std::max(1, (flen + lcap - 1) / lcap);
-  const int LMAX = std::max(4, ((flen + nsub_chunks - 1) / nsub_chunks + 3) / 4 * 4);
+  // the steps' subdomains in groups of at most kStepListMax, each with the
+  // longest input face (its chunking) and its row-tile count.  RW 16-row
+  // tiles per workgroup, the sum split in NWV / RW parts.  The split fixes
+  // the order in which a column's partial sums are added, so it is chosen
+  // from the step's shape only (rows and subdomains), never from the column
+  // count: a column's result is then the same whichever columns share the
+  // launch.  Two tiles while one column group of two-tile workgroups fits
+  // in kSweepRows workgroups, four on larger steps (measured: two tiles
+  // best at 1024^2 with 16 RHS, four on the large steps at 2048^2 with 64
+  // RHS)
+  struct HostGroup {
+    StepGroup d;
+    int flen, rw;
+  };
+  std::vector<HostGroup> hg;
+  for (int i = 0; i < nst; ++i) {
+    const int L = sidx[i] / sc.nsteps;
+    const int off = sc.step_off[sidx[i]], cnt = sc.step_cnt[sidx[i]];
+    if (cnt == 0) continue;
+    FaceSet fin{}, fout{};
+    int nin = 0;
+    const int nout = step_faces(c, L, fin, fout, &nin);
+    if (nout == 0) continue;
+    int flen = 0;
+    for (int q = 0; q < fin.n; ++q) flen = std::max(flen, 2 * g.side_len[fin.face[q]]);
+    for (int b0 = 0; b0 < cnt; b0 += kStepListMax) {
+      HostGroup h{};
+      h.d.L = L;
+      h.d.nout = nout;
+      h.d.add_y = L == 0 ? 1 : 0;
+      h.d.n = std::min(kStepListMax, cnt - b0);
+      h.d.first = off + b0;              // into step_subs until packed
+      h.d.fin = fin;
+      h.d.fout = fout;
+      h.flen = flen;
+      const long long wg2 = 8LL * (((nout + 31) / 32 + 7) / 8) * h.d.n;
+      h.rw = c->tune.sweep_rw ? c->tune.sweep_rw : (wg2 > kSweepRows ? 4 : 2);
+      hg.push_back(h);
+    }
+  }
+  const int nhg = (int)hg.size();
   // 4-deep slices of T per register batch (two batches in flight): by
   // default a wave's 20 (complex64) or 10 (complex128) slices of a 1024^2
   // face chunk in two batches (measured: complex64 8 -> 10 shortens the step
@@ -1843,54 +1934,70 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
   // choose another compiled depth (sweep_kb).  The depth does not change
   // the order of the sum.
   const int kb_sel = c->tune.sweep_kb ? c->tune.sweep_kb : (sizeof(T) == 4 ? 10 : 5);
-  // the step's subdomains in launches of at most kStepListMax
-  for (int b0 = 0; b0 < cnt; b0 += kStepListMax) {
-    StepList sl{};
-    sl.n = std::min(kStepListMax, cnt - b0);
-    for (int i = 0; i < sl.n; ++i) {
-      sl.sub[i] = c->sch.step_subs[off + b0 + i];
-      sl.op[i] = c->op_of_sub[sl.sub[i]];
+  for (int i = 0; i < nhg;) {
+    // the next group shares the launch when its row-tile count agrees
+    const int j = (i + 1 < nhg && hg[i + 1].rw == hg[i].rw) ? i + 2 : i + 1;
+    StepLaunch sl{};
+    sl.ng = j - i;
+    int pos = 0;
+    for (int k = i; k < j; ++k) {
+      StepGroup d = hg[k].d;
+      for (int t = 0; t < d.n; ++t) {
+        sl.sub[pos + t] = sc.step_subs[d.first + t];
+        sl.op[pos + t] = c->op_of_sub[sl.sub[pos + t]];
+      }
+      d.first = pos;
+      pos += d.n;
+      sl.g[k - i] = d;
     }
-    // RW 16-row tiles per workgroup, the sum split in 8 / RW parts.  The
-    // split fixes the order in which a column's partial sums are added, so
-    // it is chosen from the step's shape only (rows and subdomains), never
-    // from the column count: a column's result is then the same whichever
-    // columns share the launch.  Two tiles while one column group of
-    // two-tile workgroups fits in kSweepRows workgroups, four on larger
-    // steps (measured: two tiles best at 1024^2 with 16 RHS, four on the
-    // large steps at 2048^2 with 64 RHS)
-    auto launch_kb = [&](auto rw, auto kbc) -> hipError_t {
+    // NWV waves per workgroup: eight (one workgroup per CU, the LDS holds
+    // long face chunks) or four (two workgroups per CU, shorter chunks),
+    // chosen per shape by the autotuner
+    auto launch_kb = [&](auto rw, auto kbc, auto nwv) -> hipError_t {
       constexpr int RW = decltype(rw)::value;
       constexpr int KB = decltype(kbc)::value;
-      const int nrt = (nout + 16 * RW - 1) / (16 * RW);
-      // LDS: the staged operand pairs, or the KH partial tiles of the sum
-      size_t lds = std::max<size_t>((size_t)2 * LMAX * kSweepRS,
-                                    (size_t)(8 / RW) * 16 * 16 * RW) * sizeof(cpx<T>);
-      dim3 grid(8 * ((nrt * sl.n + 7) / 8), Cp / 16, 1);
-      hipLaunchKernelGGL((k_sweep_step<T, KB, RW>), grid, dim3(512), lds, c->stream,
-                         (const cpx<T>*)c->d_T, (const cpx<T>*)c->d_cface,
-                         (cpx<T>*)c->d_slots, (const cpx<T>*)c->d_y, sl, L, C, fin, fout, nout,
-                         L == 0 ? 1 : 0, LMAX, nsub_chunks, c->gd);
+      constexpr int NWV = decltype(nwv)::value;
+      // LDS chunks of one input face (or a part of it): 2 tiles x LMAX rows
+      // of kSweepRS operand pairs, LMAX a multiple of 4 no larger than lcap
+      const int lcap = sweep_lcap<T, NWV>();
+      size_t lds_pairs = (size_t)(NWV / RW) * 16 * 16 * RW;   // the KH partial tiles
+      int np = 0;
+      for (int k = 0; k < sl.ng; ++k) {
+        StepGroup& d = sl.g[k];
+        const int flen = hg[i + k].flen;
+        d.nsub_chunks = std::max(1, (flen + lcap - 1) / lcap);
+        d.LMAX = std::max(4, ((flen + d.nsub_chunks - 1) / d.nsub_chunks + 3) / 4 * 4);
+        lds_pairs = std::max(lds_pairs, (size_t)2 * d.LMAX * kSweepRS);
+        np += (d.nout + 16 * RW - 1) / (16 * RW) * d.n;
+      }
+      dim3 grid(8 * ((np + 7) / 8), Cp / 16, 1);
+      hipLaunchKernelGGL((k_sweep_step<T, KB, RW, NWV>), grid, dim3(NWV * 64),
+                         lds_pairs * sizeof(cpx<T>), c->stream, (const cpx<T>*)c->d_T,
+                         (const cpx<T>*)c->d_cface, (cpx<T>*)c->d_slots,
+                         (const cpx<T>*)c->d_y, sl, C, c->gd);
       return hipGetLastError();
     };
-    auto launch = [&](auto rw) -> hipError_t {
+    auto launch_nw = [&](auto rw, auto nwv) -> hipError_t {
       if constexpr (sizeof(T) == 4) {
-        if (kb_sel == 6) return launch_kb(rw, std::integral_constant<int, 6>{});
-        if (kb_sel == 8) return launch_kb(rw, std::integral_constant<int, 8>{});
-        if (kb_sel == 10) return launch_kb(rw, std::integral_constant<int, 10>{});
+        if (kb_sel == 6) return launch_kb(rw, std::integral_constant<int, 6>{}, nwv);
+        if (kb_sel == 8) return launch_kb(rw, std::integral_constant<int, 8>{}, nwv);
+        if (kb_sel == 10) return launch_kb(rw, std::integral_constant<int, 10>{}, nwv);
       } else {
-        if (kb_sel == 3) return launch_kb(rw, std::integral_constant<int, 3>{});
-        if (kb_sel == 4) return launch_kb(rw, std::integral_constant<int, 4>{});
-        if (kb_sel == 5) return launch_kb(rw, std::integral_constant<int, 5>{});
-        if (kb_sel == 6) return launch_kb(rw, std::integral_constant<int, 6>{});
+        if (kb_sel == 3) return launch_kb(rw, std::integral_constant<int, 3>{}, nwv);
+        if (kb_sel == 4) return launch_kb(rw, std::integral_constant<int, 4>{}, nwv);
+        if (kb_sel == 5) return launch_kb(rw, std::integral_constant<int, 5>{}, nwv);
+        if (kb_sel == 6) return launch_kb(rw, std::integral_constant<int, 6>{}, nwv);
       }
       return hipErrorInvalidValue;   // not a compiled depth (checked when set)
     };
-    const long long wg2 = 8LL * (((nout + 31) / 32 + 7) / 8) * sl.n;
-    const int rw_sel = c->tune.sweep_rw ? c->tune.sweep_rw : (wg2 > kSweepRows ? 4 : 2);
-    hipError_t e = rw_sel == 4 ? launch(std::integral_constant<int, 4>{})
-                               : launch(std::integral_constant<int, 2>{});
+    auto launch = [&](auto rw) -> hipError_t {
+      if (c->tune.sweep_nw == 4) return launch_nw(rw, std::integral_constant<int, 4>{});
+      return launch_nw(rw, std::integral_constant<int, 8>{});
+    };
+    hipError_t e = hg[i].rw == 4 ? launch(std::integral_constant<int, 4>{})
+                                 : launch(std::integral_constant<int, 2>{});
     if (e != hipSuccess) return e;
+    i = j;
   }
   return hipSuccess;
 }
@@ -1898,7 +2005,7 @@ hipError_t launch_sweep_step(hdsw_ctx* c, int L, int st, int off, int cnt, int C
 #define HDSW_INST2(T)                                                          \
   template hipError_t launch_block_solve<T>(hdsw_ctx*, int, const int*, int);  \
   template hipError_t launch_factor_step<T>(hdsw_ctx*, int, int);              \
-  template hipError_t launch_sweep_step<T>(hdsw_ctx*, int, int, int, int, int);\
+  template hipError_t launch_sweep_steps<T>(hdsw_ctx*, const int*, int, int);\
   template hipError_t launch_face_coef<T>(hdsw_ctx*);
 HDSW_INST2(float)
 HDSW_INST2(double)

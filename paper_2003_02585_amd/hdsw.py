@@ -55,7 +55,8 @@ class hdsw_options(ctypes.Structure):
 
 class hdsw_tuning(ctypes.Structure):
     _fields_ = [("solve_ng", ctypes.c_int), ("sweep_rw", ctypes.c_int),
-                ("sweep_kb", ctypes.c_int), ("gemm_skinny", ctypes.c_int)]
+                ("sweep_kb", ctypes.c_int), ("gemm_skinny", ctypes.c_int),
+                ("sweep_nw", ctypes.c_int), ("sweep_sched", ctypes.c_int)]
 
 
 class hdsw_solve_info(ctypes.Structure):
@@ -339,7 +340,8 @@ def hdsw_batch_take(ctx, slot, x=None):
     _check(_lib.hdsw_batch_take(ctx, int(slot), xp), "hdsw_batch_take")
 
 
-TUNING_FIELDS = ("solve_ng", "sweep_rw", "sweep_kb", "gemm_skinny")
+TUNING_FIELDS = ("solve_ng", "sweep_rw", "sweep_kb", "gemm_skinny", "sweep_nw",
+                 "sweep_sched")
 
 
 def hdsw_tuning_set(ctx, **fields):

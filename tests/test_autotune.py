@@ -17,7 +17,8 @@ def test_shape_key_names_what_decides_performance():
 def test_search_space_holds_only_compiled_values():
     c64 = A.candidates(2, True)
     c128 = A.candidates(2, False)
-    assert len(c64) == 2 * 2 * 3 and len(c128) == 2 * 4
+    assert len(c64) == 2 * 2 * 3 * 2 and len(c128) == 2 * 4 * 2 - 2
+    assert {c["sweep_nw"] for c in c64} == {4, 8}
     assert {c["sweep_kb"] for c in c64} == {6, 8, 10}
     assert {c["sweep_kb"] for c in c128} == {3, 4, 5, 6}
     assert {c["solve_ng"] for c in c128} == {1}
@@ -37,10 +38,11 @@ def test_cache_round_trip(tmp_path):
 
 def test_committed_cache_is_valid():
     for key, e in A.load().items():
-        assert set(e["params"]) == {"solve_ng", "sweep_rw", "sweep_kb", "gemm_skinny"}
+        assert set(e["params"]) == {"solve_ng", "sweep_rw", "sweep_kb", "gemm_skinny",
+                                    "sweep_nw", "sweep_sched"}
         assert e["ms"] <= e["default_ms"] + 1e-9, key
         dim = int(key.split()[0][1:])
         mixed = " c64 " in key
         allowed = A.candidates(dim, mixed) + [dict(solve_ng=0, sweep_rw=0, sweep_kb=0,
-                                                   gemm_skinny=0)]
+                                                   gemm_skinny=0, sweep_nw=0, sweep_sched=0)]
         assert e["params"] in allowed, key

@@ -239,6 +239,48 @@ def test_dedup_is_invisible(H):
     assert np.array_equal(out[0], out[1])
 
 
+# launches of the sweep steps per DDM application, one per step in sweep
+# order and one per level of the slot dependences (each subdomain's sweep
+# after every trace its slot receives and after its own previous sweep; the
+# counts are those of the rule restated in tests/test_sweep_levels.py)
+MERGE_CASES = [
+    ((48, 8, (3, 3), 1.5, 2), 40, 32),
+    ((40, 6, (1, 4), 1.5, 2), 32, 20),
+    ((45, 4, (3, 5), 1.5, 2), 56, 40),
+    ((40, 6, (4, 1), None, 1), 16, 16),   # a line of subdomains: nothing to merge
+    ((256, 4, (32, 32), 1.5, 2), 504, 380),   # two subdomain groups per step
+]
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("case,per_step,merged", MERGE_CASES)
+def test_merged_sweep_steps_change_nothing(H, prec, case, per_step, merged):
+    # the steps of one level share a launch by default; every slot still
+    # receives its additions in sweep order, so the result is the one of
+    # one launch per step, bit for bit, over two column groups
+    N, W, P, layer, rounds = case
+    c = _case(N, W, P, layer, nrhs=20)
+    _say(f"merged sweep steps {prec} N={N} P={P} rounds={rounds}")
+    ctx = _ctx(H, c, precision=H.HDSW_MIXED if prec == "mixed" else H.HDSW_FP64,
+               rounds=rounds)
+    try:
+        r = torch.from_numpy(c["b"]).cuda()
+        out, launches = {}, {}
+        for sched in (1, 2, 0):
+            H.hdsw_tuning_set(ctx, sweep_sched=sched)
+            H.hdsw_timing_enable(ctx, 2)
+            H.hdsw_timing_get(ctx, 1)
+            z = torch.zeros_like(r)
+            H.hdsw_apply_precond(ctx, r, z, r.shape[0])
+            launches[sched] = H.hdsw_timing_get(ctx, 1)[1]
+            H.hdsw_timing_enable(ctx, False)
+            out[sched] = z.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    assert launches == {1: per_step, 2: merged, 0: merged}
+    assert np.array_equal(out[1], out[2]) and np.array_equal(out[0], out[2])
+
+
 def test_batch_invariance(H):
     # each RHS alone equals the same RHS inside a batch, bit for bit
     c = _case(48, 8, (3, 3), None, nrhs=4)

@@ -53,7 +53,7 @@ def test_every_candidate_matches_the_oracle(H, prec):
         r = torch.from_numpy(b).cuda()
         z = torch.zeros_like(r)
         for bad in (dict(solve_ng=3), dict(sweep_rw=3), dict(sweep_kb=7 if mixed else 8),
-                    dict(gemm_skinny=5)):
+                    dict(gemm_skinny=5), dict(sweep_nw=2)):
             with pytest.raises(H.HdswError) as ei:
                 H.hdsw_tuning_set(ctx, **bad)
             assert ei.value.status == H.HDSW_EINVAL
@@ -66,10 +66,11 @@ def test_every_candidate_matches_the_oracle(H, prec):
             e = max(np.linalg.norm(got[i] - o) / np.linalg.norm(o) for i, o in zip(pick, oref))
             assert e < (2e-4 if mixed else 1e-10), (cand, e)
             # columns per workgroup and batch depth never change a result
-            if cand["sweep_rw"] in by_rw:
-                assert np.array_equal(got, by_rw[cand["sweep_rw"]]), cand
+            split = (cand["sweep_rw"], cand["sweep_nw"])
+            if split in by_rw:
+                assert np.array_equal(got, by_rw[split]), cand
             else:
-                by_rw[cand["sweep_rw"]] = got
+                by_rw[split] = got
     finally:
         H.hdsw_destroy(ctx)
 
