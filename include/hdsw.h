@@ -204,11 +204,15 @@ hdsw_status hdsw_query(const hdsw_ctx* ctx, size_t* factor_bytes,
 
 /* Kernel timing: HIP events bracket every launch of the enabled kernel
  * classes (0 = batched block solve, 1 = sweep step, 2 = block
- * factorization, 3 = FP64 residual) on the context's stream.  `enable` is a
- * bit mask of classes (bit k enables class k, 0 disables timing); events
- * add a few microseconds between launches, so time only what is needed.
- * hdsw_timing_get returns the accumulated milliseconds, launch count and
- * the algorithmic flops and bytes of those launches, then resets them. */
+ * factorization, 3 = FP64 residual, 4 = the source-driven 2D block solve of
+ * a DDM application, which skips (subdomain, 8-column) pairs whose
+ * right-hand side is zero; class 0 then holds the other block solves) on
+ * the context's stream.  `enable` is a bit mask of classes (bit k enables
+ * class k, 0 disables timing); events add a few microseconds between
+ * launches, so time only what is needed.  hdsw_timing_get returns the
+ * accumulated milliseconds, launch count and the algorithmic flops and
+ * bytes of those launches (0 for class 4, whose work depends on the
+ * data), then resets them. */
 hdsw_status hdsw_timing_enable(hdsw_ctx* ctx, int enable);
 hdsw_status hdsw_timing_get(hdsw_ctx* ctx, int which, double* total_ms,
                             long long* launches, double* flops, double* bytes);

@@ -132,7 +132,7 @@ hdsw_status hdsw_query(const hdsw_ctx* ctx, size_t* factor_bytes, int* n_distinc
 
 hdsw_status hdsw_timing_enable(hdsw_ctx* ctx, int enable) {
   if (!ctx) return HDSW_EINVAL;
-  ctx->tm.mask = enable & 15;
+  ctx->tm.mask = enable & 31;
   return HDSW_OK;
 }
 

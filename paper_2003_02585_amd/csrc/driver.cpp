@@ -824,9 +824,10 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
   if (C > c->Cmax) {
     graphs_clear(c);   // captured applications hold the old workspace addresses
     void* ptrs[] = {c->d_panel, c->d_slots, c->d_g, c->d_srcsum, c->d_y, c->d_out, c->d_gpart,
-                    c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm};
+                    c->d_xg, c->d_rg, c->d_bg, c->d_part, c->d_norm, c->d_nzflag};
     for (void* p : ptrs) dev_free(c, p);
     c->d_panel = c->d_slots = c->d_g = c->d_srcsum = c->d_y = c->d_out = c->d_gpart = nullptr;
+    c->d_nzflag = nullptr;
     c->gpart_bytes = 0;
     c->d_xg = c->d_rg = c->d_bg = nullptr;
     c->d_part = c->d_norm = nullptr;
@@ -844,6 +845,7 @@ static hdsw_status ensure_ws(hdsw_ctx* c, int C, bool need_gmres) {
     WALLOC(c->d_slots, iface * c->sch.nsweeps);
     WALLOC(c->d_srcsum, iface);
     WALLOC(c->d_y, iface);
+    if (g.dim == 2) WALLOC(c->d_nzflag, (size_t)g.nsub * ((C + 7) / 8) * sizeof(int));
     if (g.dim == 3) {
       // the step GEMM's B operand: trace sources in the padded k space of T
       WALLOC(c->d_g, (size_t)g.nsub * ((C + 15) / 16 * 16) * (size_t)c->t_nkt * c->t_tk * e);
@@ -901,8 +903,22 @@ static hdsw_status ddm_impl(hdsw_ctx* c, const c128* r, c128* out, int C, int ac
   const double solve_fl = 8.0 * (2.0 * g.K - 1) * g.n * (double)g.n * C * g.nsub;
   const double solve_by = 2.0 * g.K * (double)g.n * g.n * e * c->nops +
                           4.0 * g.K * (double)g.n * C * e * g.nsub;
-  HCHK(launch_fill_panel<T>(c, 0, g.nsub, c->d_all_subs, C, r, 0));
-  {
+  // the source-driven solve: (subdomain, 8-column) pairs whose right-hand
+  // side is zero (most of them for compact sources) are skipped in 2D, once
+  // the solve runs more than two rounds of 8-column workgroups on the 256
+  // CUs (below that the launch lasts one workgroup's chain however many
+  // return early, and the flags only cost time).  Skipping never changes a
+  // result, so the rule may depend on the column count.  The solve is timed
+  // as its own class then, without flops: the solve class's flops assume
+  // every pair
+  const bool skip = (long long)((C + 7) / 8) * g.nsub * 2 > 2 * 256;
+  int* nzf = skip ? c->d_nzflag : nullptr;
+  if (nzf) HCHK(launch_zero(c, nzf, (size_t)g.nsub * ((C + 7) / 8) * sizeof(int)));
+  HCHK(launch_fill_panel<T>(c, 0, g.nsub, c->d_all_subs, C, r, 0, nzf));
+  if (nzf) {
+    TimedScope ts(c, KT_SOLVE_SRC, 0, 0);
+    HCHK(launch_block_solve<T>(c, g.nsub, c->d_op_of_sub, C, nzf));
+  } else {
     TimedScope ts(c, KT_SOLVE, solve_fl, solve_by);
     HCHK(launch_block_solve<T>(c, g.nsub, c->d_op_of_sub, C));
   }
@@ -1302,7 +1318,7 @@ hdsw_status batch_take(hdsw_ctx* c, int slot, c128* x) {
 
 hdsw_status timing_get(hdsw_ctx* c, int which, double* ms, long long* n, double* fl,
                        double* by) {
-  if (which < 0 || which > 3) return HDSW_EINVAL;
+  if (which < 0 || which > KT_SOLVE_SRC) return HDSW_EINVAL;
   resolve_timing(c);
   if (ms) *ms = c->tm.ms[which];
   if (n) *n = c->tm.launches[which];

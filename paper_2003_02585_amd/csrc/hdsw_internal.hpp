@@ -178,10 +178,10 @@ struct TuneParams {
 
 struct Timing {
   int mask = 0;                     // bit k: time kernel class k
-  double ms[4] = {0, 0, 0, 0};
-  long long launches[4] = {0, 0, 0, 0};
-  double flops[4] = {0, 0, 0, 0};
-  double bytes[4] = {0, 0, 0, 0};
+  double ms[5] = {0, 0, 0, 0, 0};
+  long long launches[5] = {0, 0, 0, 0, 0};
+  double flops[5] = {0, 0, 0, 0, 0};
+  double bytes[5] = {0, 0, 0, 0, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -261,6 +261,8 @@ struct hdsw_ctx {
   void* d_out = nullptr;            // [nsub][C][NI] step outputs (3D)
   void* d_gpart = nullptr;          // split-sum partial products (3D plane solves)
   size_t gpart_bytes = 0;
+  int* d_nzflag = nullptr;          // 2D: [nsub][ceil(C / 8)] nonzero right-hand side of
+                                    // the source-driven block solve (0: skipped)
   hdsw::c128* d_xg = nullptr;       // [C][glob] iterate (FP64)
   hdsw::c128* d_rg = nullptr;       // [C][glob] residual (FP64)
   hdsw::c128* d_bg = nullptr;       // [C][glob] right-hand side (FP64)
@@ -301,7 +303,10 @@ struct hdsw_ctx {
 namespace hdsw {
 
 // kernel classes for timing
-enum { KT_SOLVE = 0, KT_GEMM = 1, KT_FACTOR = 2, KT_RESID = 3 };
+// kernel classes of the timing API; KT_SOLVE_SRC is the source-driven 2D
+// block solve, whose work depends on where the right-hand side is nonzero
+// (timed without flops or bytes)
+enum { KT_SOLVE = 0, KT_GEMM = 1, KT_FACTOR = 2, KT_RESID = 3, KT_SOLVE_SRC = 4 };
 
 // Complex GEMM on the matrix cores (big.hip):
 struct GemmArgs {
@@ -352,10 +357,10 @@ template <class T>
 hipError_t launch_factor_step(hdsw_ctx* c, int step, int middle);
 template <class T>
 hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids,
-                             int C, const c128* rglob, int unit_col0);
+                             int C, const c128* rglob, int unit_col0, int* nzflag = nullptr);
 template <class T>
 hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops_of_batch,
-                              int C);
+                              int C, const int* nzflag = nullptr);
 template <class T>
 hipError_t launch_extract_iface(hdsw_ctx* c, int nbatch, int C, void* dst,
                                 long long dst_stride_batch, int dst_ld);

@@ -316,11 +316,19 @@ __global__ void k_source_sum(cpx<T>* srcsum, const cpx<T>* __restrict__ slots,
 // any entry is written, so each thread keeps several loads in flight.
 constexpr int kFillEPT = 4;
 
+// nzflag (mode 0, may be null): nzflag[b * ceil(C / 8) + col / 8] is set
+// to 1 where batch entry b has a nonzero right-hand side entry in one of
+// the 8 columns; the block solve skips the pairs left at 0.  Each thread
+// marks the groups of its nonzero entries in a 64-bit mask relative to the
+// group of the span's first entry (the host passes nzflag only when a span
+// of blockDim * kFillEPT entries cannot reach 64 groups), the masks are
+// ORed across each wave by shuffles and across the workgroup in LDS, and
+// one lane sets the flags.
 template <class T>
 __global__ void k_fill_panel(cpx<T>* __restrict__ panel, int mode, const int* __restrict__ ids,
                              int C, const c128* __restrict__ rg,
                              const cpx<T>* __restrict__ srcsum, GeoDev g, long long glob,
-                             int col0) {
+                             int col0, int* __restrict__ nzflag) {
   // grid: x over the entries (k, column, p) of one batch entry, flat so that
   // every lane works, y over the batch entry b (its subdomain is uniform per
   // workgroup); 32-bit index arithmetic
@@ -342,7 +350,12 @@ __global__ void k_fill_panel(cpx<T>* __restrict__ panel, int mode, const int* __
   const int s = ids[b];
   const Loc sc = sub_coords(g, s);
   const unsigned span = blockDim.x * kFillEPT;
-  for (unsigned r0 = blockIdx.x * span + threadIdx.x; r0 < per; r0 += gridDim.x * span) {
+  const bool flags = mode == 0 && nzflag != nullptr;
+  const int ng8 = (C + 7) / 8;
+  __shared__ unsigned long long nzm;
+  // uniform loop bounds: every thread runs every span (the reductions below)
+  for (unsigned base = blockIdx.x * span; base < per; base += gridDim.x * span) {
+    const unsigned r0 = base + threadIdx.x;
     c128 gv[kFillEPT];
     long long gi[kFillEPT];                     // index into rg, -1: not owned / past the end
 #pragma unroll
@@ -357,12 +370,19 @@ __global__ void k_fill_panel(cpx<T>* __restrict__ panel, int mode, const int* __
       }
       gv[j] = rg[gi[j] >= 0 ? gi[j] : 0];
     }
+    // column group of the span's first entry
+    const int ga = (int)((base % cn) / n) / 8;
+    unsigned long long m = 0;
 #pragma unroll
     for (int j = 0; j < kFillEPT; ++j) {
       const unsigned r = r0 + j * blockDim.x;
       if (r < per) {
         cpx<T> v = mk<T>(T(0), T(0));
         if (gi[j] >= 0) v = ccast<T>(gv[j]);
+        if (flags && (v.re != T(0) || v.im != T(0))) {
+          const int gq = (int)((r % cn) / n) / 8;
+          m |= 1ull << ((gq - ga + ng8) % ng8);
+        }
         if (mode == 1) {
           const int k = (int)(r / cn), rem = (int)(r - (unsigned)k * cn);
           const int col = rem / n, p = rem - col * n;
@@ -376,12 +396,27 @@ __global__ void k_fill_panel(cpx<T>* __restrict__ panel, int mode, const int* __
         pb[r] = v;
       }
     }
+    if (flags) {
+      if (threadIdx.x == 0) nzm = 0;
+      __syncthreads();
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o);
+      if ((threadIdx.x & 63) == 0 && m) atomicOr(&nzm, m);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (unsigned long long mm = nzm; mm; mm &= mm - 1) {
+          const int d = __builtin_ctzll(mm);
+          atomicOr(nzflag + (size_t)b * ng8 + (ga + d) % ng8, 1);
+        }
+      }
+      __syncthreads();   // nzm is cleared by the next span
+    }
   }
 }
 
 template <class T>
 hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids,
-                             int C, const c128* rglob, int unit_col0) {
+                             int C, const c128* rglob, int unit_col0, int* nzflag) {
   const Geometry& g = c->g;
   if (nbatch > 65535) return hipErrorInvalidValue;
   const long long per = (long long)g.K * C * g.n;
@@ -404,9 +439,12 @@ hipError_t launch_fill_panel(hdsw_ctx* c, int mode, int nbatch, const int* d_ids
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  // the column-group flags: a span of 256 kFillEPT entries covers at most
+  // span / (8 n) + 3 groups, which must stay below the 64 bits of a mask
+  if (mode == 0 && nzflag && 256 * kFillEPT / (8 * g.n) + 3 >= 64) nzflag = nullptr;
   hipLaunchKernelGGL(k_fill_panel<T>, grid, dim3(256), 0, c->stream,
                      (cpx<T>*)c->d_panel, mode, d_ids, C, rglob,
-                     (const cpx<T>*)c->d_srcsum, c->gd, g.glob_nodes, unit_col0);
+                     (const cpx<T>*)c->d_srcsum, c->gd, g.glob_nodes, unit_col0, nzflag);
   return hipGetLastError();
 }
 
@@ -836,7 +874,7 @@ hipError_t launch_scale(hdsw_ctx* c, c128* dst, const c128* src, const double* i
 #define HDSW_INST(T)                                                                  \
   template hipError_t launch_cast_coef<T>(hdsw_ctx*);                                \
   template hipError_t launch_fill_panel<T>(hdsw_ctx*, int, int, const int*, int,     \
-                                           const c128*, int);                        \
+                                           const c128*, int, int*);                  \
   template hipError_t launch_extract_iface<T>(hdsw_ctx*, int, int, void*, long long, \
                                               int);                                  \
   template hipError_t launch_write_owned<T>(hdsw_ctx*, int, c128*, int);

@@ -246,7 +246,8 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
                                                        const cpx<T>* __restrict__ coefT,
                                                        size_t cstride, cpx<T>* panel,
                                                        const int* __restrict__ ops, GeoDev g,
-                                                       int C, int nbatch) {
+                                                       int C, int nbatch,
+                                                       const int* __restrict__ nzflag) {
   extern __shared__ unsigned char smem_raw[];
   constexpr int NT = NW * 64;
   const int n = g.n, nP = g.nP, K = g.K, mid = g.mid;
@@ -254,6 +255,17 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const cpx<T>* __restrict_
   if (b >= nbatch) return;
   constexpr int NCOL = 8 * NG;                    // columns of the workgroup
   const int c0 = blockIdx.x * NCOL, nc = min(NCOL, C - c0);
+  if (nzflag) {
+    // a right-hand side that is zero in all of the workgroup's columns
+    // solves to zero, which the panel already holds (both chains and both
+    // passes skip alike, so the scratch lines are never read)
+    const int* fl = nzflag + (size_t)b * ((C + 7) / 8) + c0 / 8;
+    int any = 0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+      if (c0 + 8 * q < C) any |= fl[q];
+    if (!any) return;
+  }
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cpx<T>* vb0 = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* vb1 = vb0 + NCOL * nP;
@@ -324,7 +336,8 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
                                                        const cpx<T>* __restrict__ coefT,
                                                        size_t cstride, cpx<T>* panel,
                                                        const int* __restrict__ ops, GeoDev g,
-                                                       int C, int nbatch) {
+                                                       int C, int nbatch,
+                                                       const int* __restrict__ nzflag) {
   extern __shared__ unsigned char smem_raw[];
   constexpr int NT = NW * 64;
   const int n = g.n, nP = g.nP, K = g.K, mid = g.mid;
@@ -332,6 +345,17 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const cpx<T>* __restrict_
   if (b >= nbatch) return;
   constexpr int NCOL = 8 * NG;                    // columns of the workgroup
   const int c0 = blockIdx.x * NCOL, nc = min(NCOL, C - c0);
+  if (nzflag) {
+    // a right-hand side that is zero in all of the workgroup's columns
+    // solves to zero, which the panel already holds (both chains and both
+    // passes skip alike, so the scratch lines are never read)
+    const int* fl = nzflag + (size_t)b * ((C + 7) / 8) + c0 / 8;
+    int any = 0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+      if (c0 + 8 * q < C) any |= fl[q];
+    if (!any) return;
+  }
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cpx<T>* vb0 = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* vb1 = vb0 + NCOL * nP;
@@ -441,7 +465,8 @@ struct SolveKSB {
 };
 
 template <class T, int MAXT, int NW, int NG>
-static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
+static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int C,
+                                 const int* nzflag) {
   constexpr int EPT = 2048 * NG / (NW * 64);
   const Geometry& g = c->g;
   if (8 * NG * g.n > EPT * NW * 64) return hipErrorInvalidValue;
@@ -450,23 +475,24 @@ static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int 
   size_t xstride = (size_t)g.K * g.nP * g.nP;
   hipLaunchKernelGGL((k_solve_fwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT, NG>), grid, dim3(NW * 64), lds,
                      c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
-                     c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
+                     c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch, nzflag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_solve_bwd<T, MAXT, SolveKSB<T, MAXT>::v, NW, EPT, NG>), grid, dim3(NW * 64), lds,
                      c->stream, (const cpx<T>*)c->d_X, xstride, (const cpx<T>*)c->d_coefT,
-                     c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch);
+                     c->coef_stride, (cpx<T>*)c->d_panel, d_ops, c->gd, C, nbatch, nzflag);
   return hipGetLastError();
 }
 
 template <class T, int NW, int NG>
-static hipError_t launch_solve_nw(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
+static hipError_t launch_solve_nw(hdsw_ctx* c, int nbatch, const int* d_ops, int C,
+                                  const int* nz) {
   const int nMt = c->g.nP / 16;
   const int th = (nMt + 1) / 2;
-  if (th <= 2) return launch_solve_t<T, 2, NW, NG>(c, nbatch, d_ops, C);
-  if (th <= 3) return launch_solve_t<T, 3, NW, NG>(c, nbatch, d_ops, C);
-  if (th <= 5) return launch_solve_t<T, 5, NW, NG>(c, nbatch, d_ops, C);
-  if (th <= 8) return launch_solve_t<T, 8, NW, NG>(c, nbatch, d_ops, C);
+  if (th <= 2) return launch_solve_t<T, 2, NW, NG>(c, nbatch, d_ops, C, nz);
+  if (th <= 3) return launch_solve_t<T, 3, NW, NG>(c, nbatch, d_ops, C, nz);
+  if (th <= 5) return launch_solve_t<T, 5, NW, NG>(c, nbatch, d_ops, C, nz);
+  if (th <= 8) return launch_solve_t<T, 8, NW, NG>(c, nbatch, d_ops, C, nz);
   return hipErrorInvalidValue;   // nP <= 256 (checked at setup): at most 8 tiles per half
 }
 
@@ -475,8 +501,11 @@ hipError_t launch_big_solve(hdsw_ctx* c, int nbatch, const int* d_ops, const int
                             const int* grp_off, const int* grp_cnt, const int* ids,
                             int ngroups, int maxcnt, int C);
 
+// nzflag (2D, may be null): per (batch entry, 8 columns), 0 where the
+// right-hand side in the panel is zero; those workgroups return at once.
 template <class T>
-hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) {
+hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C,
+                              const int* nzflag) {
   if (c->g.dim == 3) {
     // plane blocks: one GEMM per plane and operator group; the batch is
     // either every subdomain (grouped by operator) or one operator's panel
@@ -498,11 +527,11 @@ hipError_t launch_block_solve(hdsw_ctx* c, int nbatch, const int* d_ops, int C) 
     const long long wg8 = (long long)((C + 7) / 8) * nbatch * 2;
     const bool wide = c->tune.solve_ng ? c->tune.solve_ng == 2 : (C >= 16 && wg8 > 2 * 256);
     if (wide && C > 8 && solve_nw<T>(c->g.nP, 2) == 8)
-      return launch_solve_nw<T, 8, 2>(c, nbatch, d_ops, C);
+      return launch_solve_nw<T, 8, 2>(c, nbatch, d_ops, C, nzflag);
   }
   const int nw = solve_nw<T>(c->g.nP, 1);
-  if (nw == 8) return launch_solve_nw<T, 8, 1>(c, nbatch, d_ops, C);
-  if (nw == 4) return launch_solve_nw<T, 4, 1>(c, nbatch, d_ops, C);
+  if (nw == 8) return launch_solve_nw<T, 8, 1>(c, nbatch, d_ops, C, nzflag);
+  if (nw == 4) return launch_solve_nw<T, 4, 1>(c, nbatch, d_ops, C, nzflag);
   return hipErrorInvalidValue;
 }
 
@@ -2003,7 +2032,7 @@ hipError_t launch_sweep_steps(hdsw_ctx* c, const int* sidx, int nst, int C) {
 }
 
 #define HDSW_INST2(T)                                                          \
-  template hipError_t launch_block_solve<T>(hdsw_ctx*, int, const int*, int);  \
+  template hipError_t launch_block_solve<T>(hdsw_ctx*, int, const int*, int, const int*); \
   template hipError_t launch_factor_step<T>(hdsw_ctx*, int, int);              \
   template hipError_t launch_sweep_steps<T>(hdsw_ctx*, const int*, int, int);\
   template hipError_t launch_face_coef<T>(hdsw_ctx*);

@@ -2,9 +2,10 @@
 // memory (code under stream capture, tight serving loops, harnesses that
 // forbid hipMalloc).  It runs the same kernels as hdsw_apply_precond, with
 // the per-call workspaces -- subdomain panels, trace slots, summed sources,
-// source-driven interface values and (3D) the step GEMM operands and
-// split-sum partials -- carved out of one file-scope device array instead of
-// the context's own allocations.
+// source-driven interface values, (2D) the nonzero flags of the
+// source-driven solve and (3D) the step GEMM operands and split-sum
+// partials -- carved out of one file-scope device array instead of the
+// context's own allocations.
 //
 // The array is a fixed kScratchBytes per device, held from the first load of
 // this library on that device until the process ends.  Its device address is
@@ -13,8 +14,8 @@
 // which in host code is a stand-in without a device address.  Every call on
 // one device shares the array, and each call leaves its contents behind:
 // everything the kernels read is written earlier in the same call (the trace
-// slots are cleared by a fill kernel), so a call never depends on what an
-// earlier call left.  Calls that overlap on one device race for the array.
+// slots and the nonzero flags are cleared by a fill kernel), so a call never
+// depends on what an earlier call left.  Calls that overlap on one device race for the array.
 #include <mutex>
 
 #include "hdsw_internal.hpp"
@@ -54,7 +55,7 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 // plane-solve sums, which depends on the partials' size) run exactly as in
 // hdsw_apply_precond.
 struct Carve {
-  size_t panel, slots, srcsum, y, g, out, gpart, gpart_bytes, total;
+  size_t panel, slots, srcsum, y, nzflag, g, out, gpart, gpart_bytes, total;
 };
 static Carve carve(const hdsw_ctx* c, int C) {
   const Geometry& g = c->g;
@@ -70,6 +71,10 @@ static Carve carve(const hdsw_ctx* c, int C) {
   o += align256(iface);
   k.y = o;
   o += align256(iface);
+  if (g.dim == 2) {
+    k.nzflag = o;
+    o += align256((size_t)g.nsub * ((C + 7) / 8) * sizeof(int));
+  }
   if (g.dim == 3) {
     k.g = o;
     o += align256((size_t)g.nsub * ((C + 15) / 16 * 16) * (size_t)c->t_nkt * c->t_tk * e);
@@ -100,7 +105,8 @@ hdsw_status apply_precond_noalloc(hdsw_ctx* c, const c128* r, c128* z, int nrhs)
   while (chunk < nrhs && carve(c, chunk + 1).total <= kScratchBytes) ++chunk;
   // the context's workspaces are set aside for the call; event timing is
   // off (its event pool would be created on first use)
-  void* saved[7] = {c->d_panel, c->d_slots, c->d_srcsum, c->d_y, c->d_g, c->d_out, c->d_gpart};
+  void* saved[8] = {c->d_panel, c->d_slots, c->d_srcsum, c->d_y, c->d_g, c->d_out, c->d_gpart,
+                    c->d_nzflag};
   const size_t saved_gpart = c->gpart_bytes;
   const int saved_mask = c->tm.mask;
   c->tm.mask = 0;
@@ -113,6 +119,7 @@ hdsw_status apply_precond_noalloc(hdsw_ctx* c, const c128* r, c128* z, int nrhs)
     c->d_slots = b + k.slots;
     c->d_srcsum = b + k.srcsum;
     c->d_y = b + k.y;
+    c->d_nzflag = c->g.dim == 2 ? (int*)(b + k.nzflag) : nullptr;
     c->d_g = c->g.dim == 3 ? b + k.g : nullptr;
     c->d_out = c->g.dim == 3 ? b + k.out : nullptr;
     c->d_gpart = c->g.dim == 3 ? b + k.gpart : nullptr;
@@ -127,6 +134,7 @@ hdsw_status apply_precond_noalloc(hdsw_ctx* c, const c128* r, c128* z, int nrhs)
   c->d_g = saved[4];
   c->d_out = saved[5];
   c->d_gpart = saved[6];
+  c->d_nzflag = (int*)saved[7];
   c->gpart_bytes = saved_gpart;
   c->tm.mask = saved_mask;
   if (st != HDSW_OK) return st;

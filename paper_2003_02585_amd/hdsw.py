@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhdsw.so")
 HDSW_OK, HDSW_EINVAL, HDSW_ENOMEM, HDSW_EDEVICE, HDSW_ENOTFACTORED, \
     HDSW_ENOCONV, HDSW_EBUSY = range(7)
 HDSW_FP64, HDSW_MIXED = 0, 1
-KT_SOLVE, KT_GEMM, KT_FACTOR, KT_RESID = range(4)
+KT_SOLVE, KT_GEMM, KT_FACTOR, KT_RESID, KT_SOLVE_SRC = range(5)
 
 EXPORTED = [
     "hdsw_default_options", "hdsw_setup", "hdsw_factor", "hdsw_solve",
@@ -286,7 +286,7 @@ def hdsw_query(ctx):
 def hdsw_timing_enable(ctx, enable=True):
     """enable: True (every kernel class), False (none) or a bit mask of
     classes (bit k = class k of hdsw_timing_get)."""
-    mask = (15 if enable else 0) if isinstance(enable, bool) else int(enable)
+    mask = (31 if enable else 0) if isinstance(enable, bool) else int(enable)
     _check(_lib.hdsw_timing_enable(ctx, mask), "hdsw_timing_enable")
 
 

@@ -281,6 +281,49 @@ def test_merged_sweep_steps_change_nothing(H, prec, case, per_step, merged):
     assert np.array_equal(out[1], out[2]) and np.array_equal(out[0], out[2])
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_zero_rhs_pairs_skip_without_changing_results(H, prec):
+    # the source-driven block solve skips (subdomain, 8-column) pairs whose
+    # right-hand side is zero once it runs more than two rounds of 8-column
+    # workgroups (37 columns on 8 x 8 subdomains: 5 groups, 640 workgroups);
+    # a column alone (128 workgroups) runs every pair.  Its result is the
+    # same either way, bit for bit, and a zero column gives zero.  Compact
+    # sources, one dense column, one zero column, a short last group
+    c = _case(128, 4, (8, 8), 1.5, nrhs=37)
+    rng = np.random.default_rng(11)
+    b = c["b"].copy()
+    b[7] = rng.standard_normal(b[7].shape) + 1j * rng.standard_normal(b[7].shape)
+    b[36] = 0
+    _say(f"zero right-hand side pairs {prec}")
+    ctx = _ctx(H, c, precision=H.HDSW_MIXED if prec == "mixed" else H.HDSW_FP64, rounds=1)
+    try:
+        r = torch.from_numpy(b).cuda()
+        z = torch.zeros_like(r)
+        H.hdsw_timing_enable(ctx, 1 << H.KT_SOLVE_SRC)
+        H.hdsw_apply_precond(ctx, r, z, r.shape[0])
+        skipped = H.hdsw_timing_get(ctx, H.KT_SOLVE_SRC)[1]
+        H.hdsw_timing_enable(ctx, False)
+        batch = z.cpu().numpy()
+        alone = {}
+        for i in (0, 6, 7, 16, 36):
+            zi = torch.zeros_like(r[i:i + 1])
+            H.hdsw_timing_enable(ctx, 1 << H.KT_SOLVE_SRC)
+            H.hdsw_apply_precond(ctx, r[i:i + 1].contiguous(), zi, 1)
+            assert H.hdsw_timing_get(ctx, H.KT_SOLVE_SRC)[1] == 0   # no skipping alone
+            H.hdsw_timing_enable(ctx, False)
+            alone[i] = zi.cpu().numpy()[0]
+    finally:
+        H.hdsw_destroy(ctx)
+    assert skipped == 1                                          # the batch skipped
+    for i, v in alone.items():
+        assert np.array_equal(batch[i], v), i
+    assert not np.any(batch[36])
+    sol = O.SubdomainSolvers(c["part"])
+    ref = O.ddm_apply(c["prob"], c["part"], b[16], rounds=1, solvers=sol)
+    e = np.linalg.norm(batch[16] - ref) / np.linalg.norm(ref)
+    assert e < (2e-4 if prec == "mixed" else 1e-10), e
+
+
 def test_batch_invariance(H):
     # each RHS alone equals the same RHS inside a batch, bit for bit
     c = _case(48, 8, (3, 3), None, nrhs=4)
