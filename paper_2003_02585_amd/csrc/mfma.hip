@@ -1560,30 +1560,30 @@ __global__ __launch_bounds__(NWV * 64) void k_sweep_step(
   const cpx<T>* b0 = bp + (size_t)kk * kSweepRS + jc;
   const cpx<T>* b1 = bp + (size_t)(LMAX + kk) * kSweepRS + jc;
   v4 aR0 = v4{T(0), T(0), T(0), T(0)}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+  // each slice's B operand is read from LDS next to its MFMAs (a batch's
+  // worth read ahead held 2 KB complex registers, which with the epilogue
+  // operands cost the second workgroup per CU)
   auto compute = [&](const cpx<T>(&a)[KB], const ChunkGeo& c, int ks0) {
-    cpx<T> p0[KB], p1[KB];
-#pragma unroll
-    for (int u = 0; u < KB; ++u) {
-      const int ks = min(ks0 + u, c.nks - 1);
-      p0[u] = b0[(size_t)ks * 4 * kSweepRS];
-      p1[u] = b1[(size_t)ks * 4 * kSweepRS];
-    }
     if (ks0 + KB <= c.kse) {
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
-        aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
-        aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
-        aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
-        aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
+        const cpx<T> p0 = b0[(size_t)(ks0 + u) * 4 * kSweepRS];
+        const cpx<T> p1 = b1[(size_t)(ks0 + u) * 4 * kSweepRS];
+        aR0 = MF<T>::mfma(a[u].re, p0.re, aR0);
+        aR1 = MF<T>::mfma(a[u].re, p1.re, aR1);
+        aI0 = MF<T>::mfma(a[u].im, p0.im, aI0);
+        aI1 = MF<T>::mfma(a[u].im, p1.im, aI1);
       }
     } else {
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         if (ks0 + u < c.kse) {
-          aR0 = MF<T>::mfma(a[u].re, p0[u].re, aR0);
-          aR1 = MF<T>::mfma(a[u].re, p1[u].re, aR1);
-          aI0 = MF<T>::mfma(a[u].im, p0[u].im, aI0);
-          aI1 = MF<T>::mfma(a[u].im, p1[u].im, aI1);
+          const cpx<T> p0 = b0[(size_t)(ks0 + u) * 4 * kSweepRS];
+          const cpx<T> p1 = b1[(size_t)(ks0 + u) * 4 * kSweepRS];
+          aR0 = MF<T>::mfma(a[u].re, p0.re, aR0);
+          aR1 = MF<T>::mfma(a[u].re, p1.re, aR1);
+          aI0 = MF<T>::mfma(a[u].im, p0.im, aI0);
+          aI1 = MF<T>::mfma(a[u].im, p1.im, aI1);
         }
       }
     }
@@ -1601,24 +1601,34 @@ __global__ __launch_bounds__(NWV * 64) void k_sweep_step(
     load(a0, cur, cur.ksb);
     stage_load(qc);
   }
-  // epilogue operands do not depend on the product: fetch them first
-  StepOut eo[NQ];
+  // The epilogue operands do not depend on the product.  They are fetched
+  // once the first chunk is staged (after the loop when there is none), so
+  // that a workgroup's first requests are only those its first chunk waits
+  // for: at the start of a launch every workgroup asks at once, and the
+  // epilogue operands in the same burst held the first chunk back about
+  // 5 us.  No workgroup of the launch writes what another reads, so when
+  // they are read does not matter.  Only the destination index stays live.
+  long long dsti[NQ];
   cpx<T> ey[NQ], ein[NQ], edst[NQ];
+  auto epi_fetch = [&]() {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    int idx = tid + q * NT;
-    int col = idx / RWS, r = idx % RWS;
-    int orow = rtile * RWS + r;
-    eo[q] = StepOut{-1, -1, -1};
-    if (idx < RWS * 16 && orow < nout && c0 + col < C)
-      eo[q] = step_out(g, fout, s, orow, c0 + col, C, L, slot_stride, add_y);
-    ey[q] = mk<T>(T(0), T(0));
-    ein[q] = ey[q];
-    edst[q] = ey[q];
-    if (eo[q].yo >= 0) ey[q] = ybuf[eo[q].yo];
-    if (eo[q].ino >= 0) ein[q] = slots[eo[q].ino];
-    if (eo[q].dst >= 0) edst[q] = slots[eo[q].dst];
-  }
+    for (int q = 0; q < NQ; ++q) {
+      int idx = tid + q * NT;
+      int col = idx / RWS, r = idx % RWS;
+      int orow = rtile * RWS + r;
+      StepOut o{-1, -1, -1};
+      if (idx < RWS * 16 && orow < nout && c0 + col < C)
+        o = step_out(g, fout, s, orow, c0 + col, C, L, slot_stride, add_y);
+      dsti[q] = o.dst;
+      ey[q] = mk<T>(T(0), T(0));
+      ein[q] = ey[q];
+      edst[q] = ey[q];
+      if (o.yo >= 0) ey[q] = ybuf[o.yo];
+      if (o.ino >= 0) ein[q] = slots[o.ino];
+      if (o.dst >= 0) edst[q] = slots[o.dst];
+    }
+  };
+  bool fetched = false;
   while (qc < nqc) {
     int qn = qc + 1;
     while (qn < nqc && chunk_len(qn) == 0) ++qn;
@@ -1627,6 +1637,10 @@ __global__ __launch_bounds__(NWV * 64) void k_sweep_step(
     stage_store(qc);
     lds_barrier();
     if (qn < nqc) stage_load(qn);              // in flight during this chunk's sum
+    if (!fetched) {
+      epi_fetch();
+      fetched = true;
+    }
     if (cur.ksb >= cur.kse) load(a0, nxt, nxt.ksb);   // no slices here: move on
     for (int ks0 = cur.ksb; ks0 < cur.kse; ks0 += 2 * KB) {
       load(a1, cur, ks0 + KB);
@@ -1638,6 +1652,7 @@ __global__ __launch_bounds__(NWV * 64) void k_sweep_step(
     qc = qn;
     cur = nxt;
   }
+  if (!fetched) epi_fetch();
   lds_barrier();
   // add the KH parts in a fixed order and stage the RWS x 16 tile:
   // part p of the sum at st + p * (2 * 16 * RWS) floats, p = 0 the final tile
@@ -1671,11 +1686,11 @@ __global__ __launch_bounds__(NWV * 64) void k_sweep_step(
   lds_barrier();
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    if (eo[q].dst < 0) continue;
+    if (dsti[q] < 0) continue;
     int idx = tid + q * NT;
     int col = idx / RWS, r = idx % RWS;
     cpx<T> v = bp[col * RWS + r] + ey[q];
-    slots[eo[q].dst] = edst[q] + (v - ein[q]);
+    slots[dsti[q]] = edst[q] + (v - ein[q]);
   }
 }
 
