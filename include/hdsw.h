@@ -134,9 +134,10 @@ void hdsw_default_options(hdsw_options* opt);
  * Errors: EINVAL (dim not 2/3, n % nsub != 0, nonpositive sizes, W < 1,
  * non-finite or nonpositive k, h <= 0, bad options, only one allocator
  * hook, NULL pointers; in 2D an extended subdomain line n_x / P_x + 2 W of
- * more than 256 nodes, whose block solve would not keep its vectors and
- * register tiles on chip; in 3D an interface response beyond 32-bit
- * offsets), ENOMEM (budget or allocation), EDEVICE. */
+ * more than 384 nodes, or more than 256 with HDSW_FP64, whose block solve
+ * would not keep its vectors and register tiles on chip; in 3D an
+ * interface response beyond 32-bit offsets), ENOMEM (budget or
+ * allocation), EDEVICE. */
 hdsw_status hdsw_setup(const hdsw_grid* grid, const double* kappa_host,
                        const hdsw_partition* part, int pml_width,
                        const hdsw_options* opt, void* stream, hdsw_ctx** out);

@@ -414,9 +414,11 @@ hdsw_status setup_impl(const hdsw_grid* grid, const double* kappa, const hdsw_pa
   g.nP = (g.n + 15) / 16 * 16;
   g.mid = g.K / 2;
   g.PL = g.K + 2;
-  // the 2D block solver keeps an nP-long vector per column in LDS; 3D plane
-  // blocks go through the dense-block path
-  if (g.dim == 2 && g.nP > 256) {
+  // the 2D block solver keeps nP-long vectors per column in LDS and up to
+  // 12 row tiles per half chain in registers: complex64 lines of up to 384
+  // nodes, complex128 up to 256; 3D plane blocks go through the dense-block
+  // path
+  if (g.dim == 2 && (g.nP > 384 || (g.nP > 256 && opt->precision != HDSW_MIXED))) {
     delete c;
     return HDSW_EINVAL;
   }

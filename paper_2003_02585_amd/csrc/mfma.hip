@@ -461,13 +461,16 @@ static int solve_nw(int nP, int NG) {
 // (checked in the register report of the build for every instantiation)
 template <class T, int MAXT>
 struct SolveKSB {
-  static constexpr int v = sizeof(T) == 4 ? (MAXT <= 5 ? 5 : 2) : (MAXT == 5 ? 3 : 2);
+  static constexpr int v =
+      sizeof(T) == 4 ? (MAXT <= 5 ? 5 : MAXT <= 8 ? 2 : 1) : (MAXT == 5 ? 3 : 2);
 };
 
 template <class T, int MAXT, int NW, int NG>
 static hipError_t launch_solve_t(hdsw_ctx* c, int nbatch, const int* d_ops, int C,
                                  const int* nzflag) {
-  constexpr int EPT = 2048 * NG / (NW * 64);
+  // epilogue entries per thread: 8 NG columns of up to 256 rows (up to 384
+  // with 12 tiles per half)
+  constexpr int EPT = (MAXT <= 8 ? 2048 : 3072) * NG / (NW * 64);
   const Geometry& g = c->g;
   if (8 * NG * g.n > EPT * NW * 64) return hipErrorInvalidValue;
   dim3 grid((C + 8 * NG - 1) / (8 * NG), nbatch, 2);
@@ -493,7 +496,12 @@ static hipError_t launch_solve_nw(hdsw_ctx* c, int nbatch, const int* d_ops, int
   if (th <= 3) return launch_solve_t<T, 3, NW, NG>(c, nbatch, d_ops, C, nz);
   if (th <= 5) return launch_solve_t<T, 5, NW, NG>(c, nbatch, d_ops, C, nz);
   if (th <= 8) return launch_solve_t<T, 8, NW, NG>(c, nbatch, d_ops, C, nz);
-  return hipErrorInvalidValue;   // nP <= 256 (checked at setup): at most 8 tiles per half
+  // complex64 lines of up to 384 nodes (8 columns: the LDS holds the
+  // vectors of eight waves; setup refuses longer lines and complex128
+  // beyond 256)
+  if constexpr (sizeof(T) == 4 && NW == 8 && NG == 1)
+    if (th <= 12) return launch_solve_t<T, 12, NW, NG>(c, nbatch, d_ops, C, nz);
+  return hipErrorInvalidValue;
 }
 
 template <class T>

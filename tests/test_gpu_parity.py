@@ -324,6 +324,35 @@ def test_zero_rhs_pairs_skip_without_changing_results(H, prec):
     assert e < (2e-4 if prec == "mixed" else 1e-10), e
 
 
+def test_sec52_line_length_in_complex64(H):
+    # the subdomain size of the paper's Sec. 5.2 experiments: 300 interior
+    # nodes and a 30-node PML per side give 360-node lines (23 row tiles, 12
+    # per half chain), which the complex64 path takes; complex128 refuses
+    # lines beyond 256 nodes and both refuse beyond 384
+    c = _case(600, 30, (2, 2), None, nrhs=2)
+    sol = O.SubdomainSolvers(c["part"])
+    ref = [O.ddm_apply(c["prob"], c["part"], bi, rounds=1, solvers=sol) for bi in c["b"]]
+    _say("360-node lines, mixed")
+    ctx = _ctx(H, c, precision=H.HDSW_MIXED, rounds=1)
+    try:
+        r = torch.from_numpy(c["b"]).cuda()
+        z = torch.zeros_like(r)
+        H.hdsw_apply_precond(ctx, r, z, r.shape[0])
+        got = z.cpu().numpy()
+    finally:
+        H.hdsw_destroy(ctx)
+    e = _rel(got, ref)
+    _say(f"  rel diff {e:.3e}")
+    assert e < 2e-4
+    stream = torch.cuda.current_stream().cuda_stream
+    for N, prec in ((600, H.HDSW_FP64), (800, H.HDSW_MIXED)):
+        kap = wl.constant_kappa((N, N), 2 * np.pi / (10.0 / N))
+        with pytest.raises(H.HdswError) as ei:
+            H.hdsw_setup(kap, 1.0 / N, (2, 2), 30, H.hdsw_default_options(precision=prec),
+                         stream=stream)
+        assert ei.value.status == H.HDSW_EINVAL
+
+
 def test_batch_invariance(H):
     # each RHS alone equals the same RHS inside a batch, bit for bit
     c = _case(48, 8, (3, 3), None, nrhs=4)
