@@ -1060,16 +1060,23 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
 #pragma unroll
       for (int c2 = 0; c2 < 8; ++c2) pr[c2] = PJ[(size_t)(8 * h + c2) * nP + row];
       int mykk = -1;                                // panel column this row pivots
+      int anybad = 0;                               // a zero or NaN pivot in the panel
       const int kend = min(16, n - j0);             // padding columns: no pivot
 #pragma unroll 1
       for (int kk = 0; kk < kend; ++kk) {
-        const int j = j0 + kk, slot = kk & 1;
+        const int j = j0 + kk, slot = kk & 1, k7 = kk & 7;
         // column kk of this row, from the thread of the row that holds it
-        // (the neighbouring lane: a DPP swap within lane pairs)
-        cpx<T> own = pr[0];
-#pragma unroll
-        for (int c2 = 1; c2 < 8; ++c2)
-          if ((kk & 7) == c2) own = pr[c2];
+        // (the neighbouring lane: a DPP swap within lane pairs); the entry is
+        // picked by a select tree over the bits of kk (depth 3, not a chain
+        // of 7 dependent selects)
+        const bool b0 = k7 & 1, b1 = (k7 & 2) != 0, b2 = (k7 & 4) != 0;
+        const T s01r = b0 ? pr[1].re : pr[0].re, s01i = b0 ? pr[1].im : pr[0].im;
+        const T s23r = b0 ? pr[3].re : pr[2].re, s23i = b0 ? pr[3].im : pr[2].im;
+        const T s45r = b0 ? pr[5].re : pr[4].re, s45i = b0 ? pr[5].im : pr[4].im;
+        const T s67r = b0 ? pr[7].re : pr[6].re, s67i = b0 ? pr[7].im : pr[6].im;
+        const T s03r = b1 ? s23r : s01r, s03i = b1 ? s23i : s01i;
+        const T s47r = b1 ? s67r : s45r, s47i = b1 ? s67i : s45i;
+        const cpx<T> own = mk<T>(b2 ? s47r : s03r, b2 ? s47i : s03i);
         const cpx<T> oth = swap_pair(own);
         const cpx<T> f = h == (kk >> 3) ? own : oth;
         unsigned key = 0u;
@@ -1085,61 +1092,60 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
         }
         if (lane == 0) candk[slot * 8 + wave] = wk;
         lds_barrier();
-        // the eight offers' keys in two 16-byte reads (one wait), then the
-        // pivot entry and this thread's half of the pivot row in one batch
+        // the eight offers' keys in two 16-byte reads.  Offered keys are
+        // distinct (each carries its row) and the best one is positive (an
+        // unused row below n exists for every column j < n; padding rows
+        // start out used), so the pivot row p is a row below n and the
+        // largest key; the wave that offered it is the one holding row p
+        // (rows 32 w .. 32 w + 31, two threads per row), so no search over
+        // the offers is needed.
         const uint4* ck = reinterpret_cast<const uint4*>(candk + slot * 8);
         const uint4 k0 = ck[0], k1 = ck[1];
-        unsigned best = k0.x;
-        int bw = 0;
-        if (k0.y > best) { best = k0.y; bw = 1; }
-        if (k0.z > best) { best = k0.z; bw = 2; }
-        if (k0.w > best) { best = k0.w; bw = 3; }
-        if (k1.x > best) { best = k1.x; bw = 4; }
-        if (k1.y > best) { best = k1.y; bw = 5; }
-        if (k1.z > best) { best = k1.z; bw = 6; }
-        if (k1.w > best) { best = k1.w; bw = 7; }
-        // an unused row below n exists for every column j < n (padding rows
-        // start out used), so p is a row below n
-        const int p = 255 - (int)(best & 255u);
+        const unsigned best = max(max(max(k0.x, k0.y), max(k0.z, k0.w)),
+                                  max(max(k1.x, k1.y), max(k1.z, k1.w)));
+        const int p = 255 - (int)(best & 255u), bw = p >> 5;
         const cpx<T>* prow = candrow + (slot * 8 + bw) * 16;
-        const cpx<T> piv = prow[kk];
-        const bool bad = (piv.re == T(0) && piv.im == T(0)) || !(piv.re == piv.re) ||
-                         !(piv.im == piv.im);
-        if (bad && tid == 0) atomicExch(flag, 1);
-        const cpx<T> inv = cinv(piv);
-        // this thread's half of the pivot row (one batch of reads)
+        // this thread's half of the pivot row and the pivot entry in one
+        // batch of reads, ahead of the reciprocal
         cpx<T> ph[8];
 #pragma unroll
         for (int c2 = 0; c2 < 8; ++c2) ph[c2] = prow[8 * h + c2];
-        if (has) {
-          if (row == p) {
+        const cpx<T> piv = prow[kk];
+        anybad |= (piv.re == T(0) && piv.im == T(0)) || !(piv.re == piv.re) ||
+                  !(piv.im == piv.im);
+        const cpx<T> inv = cinv(piv);
+        // complex64: both branches read ph (the pivot row's thread finds
+        // its own row there, as it offered it), so its reads stay ahead of
+        // the reciprocal instead of sinking into one branch; complex128
+        // keeps them after it (holding them across the reciprocal would
+        // spill).  The column kk of the other rows is taken by a select,
+        // not a branch per column.
+        if (has && row == p) {
 #pragma unroll
-            for (int c2 = 0; c2 < 8; ++c2)
-              pr[c2] = 8 * h + c2 == kk ? inv : pr[c2] * inv;
-            used = true;
-            mykk = kk;
-            if (h == 0) {
-              pivr[j] = p;
-              invp[p] = j;
-            }
-          } else {
+          for (int c2 = 0; c2 < 8; ++c2)
+            pr[c2] = 8 * h + c2 == kk ? inv : (sizeof(T) == 4 ? ph[c2] : pr[c2]) * inv;
+          used = true;
+          mykk = kk;
+          if (h == 0) {
+            pivr[j] = p;
+            invp[p] = j;
+          }
+        } else {
+          const cpx<T> nfi = -(f * inv);
 #pragma unroll
-            for (int c2 = 0; c2 < 8; ++c2) {
-              if (8 * h + c2 == kk) {
-                pr[c2] = -(f * inv);
-              } else {
-                const cpx<T> r2 = ph[c2] * inv;
-                cpx<T> m = pr[c2];
-                m.re = fma(-f.re, r2.re, m.re);
-                m.re = fma(f.im, r2.im, m.re);
-                m.im = fma(-f.re, r2.im, m.im);
-                m.im = fma(-f.im, r2.re, m.im);
-                pr[c2] = m;
-              }
-            }
+          for (int c2 = 0; c2 < 8; ++c2) {
+            const cpx<T> r2 = ph[c2] * inv;
+            cpx<T> m = pr[c2];
+            m.re = fma(-f.re, r2.re, m.re);
+            m.re = fma(f.im, r2.im, m.re);
+            m.im = fma(-f.re, r2.im, m.im);
+            m.im = fma(-f.im, r2.re, m.im);
+            const bool isk = 8 * h + c2 == kk;
+            pr[c2] = mk<T>(isk ? nfi.re : m.re, isk ? nfi.im : m.im);
           }
         }
       }
+      if (anybad && tid == 0) atomicExch(flag, 1);
       // eliminated panel back to LDS; W = panel - unit vectors at the pivot
       // rows; R rows of panel columns without a pivot (padding) are zero
       if (has) {
