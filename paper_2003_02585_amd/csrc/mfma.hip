@@ -988,19 +988,50 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
   const cpx<T>* __restrict__ PB = pb2 >= 0 ? Xo + (size_t)pb2 * nP * nP : nullptr;
   // D_k = A_k - B X_{k-1} B (- B X_{k+1} B for the middle line), formed
   // column-major in the output block, then read into the accumulators
-  for (int idx = tid; idx < nP * nP; idx += 512) {
-    const int col = idx / nP, row = idx - col * nP;
-    cpx<T> v = mk<T>(T(0), T(0));
-    if (row < n && col < n) {
-      // the source is chosen as a pointer and read field by field: a struct
-      // copy under a condition would keep v in private memory
-      const cpx<T>* src = row == col ? dg + row : col == row + 1 ? ax + col
-                          : row == col + 1 ? ax + row : nullptr;
-      if (src) v = mk<T>(src->re, src->im);
-      if (PA) v = v - ay[(size_t)fa * n + row] * ay[(size_t)fa * n + col] * PA[idx];
-      if (PB) v = v - ay[(size_t)fb * n + row] * ay[(size_t)fb * n + col] * PB[idx];
+  // Four entries per thread per pass, every load of the four issued before
+  // the first use (indices clamped into the block, results masked), so the
+  // loads of a pass are in flight together instead of one entry's at a time.
+  // The operands of the neighbour's term come from a valid block even where
+  // it does not exist (PA, PB null); the term is then not applied.
+  const cpx<T>* PAs = PA ? PA : Mout;   // (may alias the output: not restrict)
+  const cpx<T>* PBs = PB ? PB : Mout;
+  const int fa0 = PA ? fa : 0, fb0 = PB ? fb : 0;
+  constexpr int FU = 4;
+  for (int i0 = tid; i0 < nP * nP; i0 += FU * 512) {
+    cpx<T> e0[FU], ar[FU], ac[FU], xa[FU], br[FU], bc[FU], xb[FU];
+    int rw[FU], cl[FU];
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int idx = min(i0 + u * 512, nP * nP - 1);
+      const int col = idx / nP, row = idx - col * nP;
+      rw[u] = row;
+      cl[u] = col;
+      const int r1 = min(row, n - 1), c1 = min(col, n - 1);
+      // the diagonal entry or the coupling to the neighbouring node, read
+      // field by field from a pointer (a struct copy under a condition
+      // would keep the value in private memory)
+      const cpx<T>* src = row == col ? dg + r1 : ax + max(r1, c1);
+      e0[u] = mk<T>(src->re, src->im);
+      ar[u] = ay[(size_t)fa0 * n + r1];
+      ac[u] = ay[(size_t)fa0 * n + c1];
+      xa[u] = PAs[(size_t)c1 * nP + r1];
+      br[u] = ay[(size_t)fb0 * n + r1];
+      bc[u] = ay[(size_t)fb0 * n + c1];
+      xb[u] = PBs[(size_t)c1 * nP + r1];
     }
-    Mout[idx] = v;
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int row = rw[u], col = cl[u];
+      if (i0 + u * 512 >= nP * nP) continue;
+      cpx<T> v = mk<T>(T(0), T(0));
+      if (row < n && col < n) {
+        const bool nb = row == col || col == row + 1 || row == col + 1;
+        if (nb) v = e0[u];
+        if (PA) v = v - ar[u] * ac[u] * xa[u];
+        if (PB) v = v - br[u] * bc[u] * xb[u];
+      }
+      Mout[(size_t)col * nP + row] = v;
+    }
   }
   __threadfence_block();
   __syncthreads();
@@ -1167,9 +1198,15 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
     }
     lds_barrier();
     // e. the panel's tiles take the eliminated panel; the pivot rows of the
-    //    other tiles, before their update, go to R
+    //    other tiles, before their update, go to R.  The pivot columns of
+    //    this lane's rows are read once per row tile (one wait), not once
+    //    per tile.
 #pragma unroll
-    for (int a = 0; a < RA; ++a)
+    for (int a = 0; a < RA; ++a) {
+      int jrow[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        jrow[i] = invp[16 * min(wr + 2 * a, nMt - 1) + MF<T>::row(ln, i)];
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         const int rt = wr + 2 * a, ct = wc + 4 * b;
@@ -1182,13 +1219,9 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
             acc[a][b][i] = srcp[pq];
           }
         } else {
-          // the four rows' pivot columns first (one wait), then the stores
-          int jr[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) jr[i] = invp[16 * rt + MF<T>::row(ln, i)];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int j = jr[i];
+            const int j = jrow[i];
             if ((j >> 4) == q && j < n) {
               T* dst = pq ? Ri : Rr;
               dst[(j & 15) * ld + 8 * ct + cq] = acc[a][b][i];
@@ -1196,6 +1229,7 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
           }
         }
       }
+    }
     lds_barrier();
     // g. M[:, rest] += W R on the matrix cores
 #pragma unroll 1
