@@ -891,8 +891,9 @@ __global__ __launch_bounds__(1024) void k_factor_reg(cpx<T>* X, size_t xstride,
 //    [Re | Im]; 8 waves form a 2 x 4 grid, wave (wr, wc) owning row tiles
 //    wr, wr + 2, .. and column tiles wc, wc + 4, ..;
 //  * columns are eliminated in panels of 16.  A panel's columns are
-//    gathered to LDS and eliminated there by one wave (in-place
-//    Gauss-Jordan restricted to the panel).  The panel column pivoted at
+//    gathered to LDS and eliminated in registers, two threads per row
+//    (in-place Gauss-Jordan restricted to the panel, one barrier per
+//    pivot).  The panel column pivoted at
 //    row p_k then holds T e_{p_k}, T the product of the panel's elementary
 //    eliminations; T differs from the identity only in the columns p_k, so
 //    T = I + W S^T with W = (eliminated panel) - (unit vectors e_{p_k}),
