@@ -973,6 +973,7 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
   unsigned* candk = reinterpret_cast<unsigned*>(candrow + 2 * 8 * 16);   // [2][8] their keys
                                                       // (16-byte aligned: offsets are
                                                       // multiples of 16 bytes)
+  T* spare = reinterpret_cast<T*>(candk + 16);        // [64 + nP] target of unused stores
   for (int i = tid; i < nP; i += 512) {
     pivr[i] = i;
     invp[i] = i < n ? (1 << 20) : i;                  // padding rows keep their place
@@ -1199,15 +1200,21 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
     }
     lds_barrier();
     // e. the panel's tiles take the eliminated panel; the pivot rows of the
-    //    other tiles, before their update, go to R.  The pivot columns of
-    //    this lane's rows are read once per row tile (one wait), not once
-    //    per tile.
+    //    other tiles, before their update, go to R.  Where each of this
+    //    lane's rows goes in R (if its pivot column lies in this panel) is
+    //    found once per row tile; every store is then issued, a row without
+    //    a place in R writing the lane's own spare slot (spare + lane + the
+    //    tile's column offset), so an entry's store is its base plus the
+    //    tile's column offset, with no branch or select of its own.
+    T* const rbase = (pq ? Ri : Rr) + cq;
 #pragma unroll
     for (int a = 0; a < RA; ++a) {
-      int jrow[4];
+      T* rp[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        jrow[i] = invp[16 * min(wr + 2 * a, nMt - 1) + MF<T>::row(ln, i)];
+      for (int i = 0; i < 4; ++i) {
+        const int j = invp[16 * min(wr + 2 * a, nMt - 1) + MF<T>::row(ln, i)];
+        rp[i] = ((j >> 4) == q && j < n) ? rbase + (j & 15) * ld : spare + ln;
+      }
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         const int rt = wr + 2 * a, ct = wc + 4 * b;
@@ -1221,13 +1228,7 @@ __global__ __launch_bounds__(512) void k_factor_mfma(cpx<T>* X, size_t xstride,
           }
         } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int j = jrow[i];
-            if ((j >> 4) == q && j < n) {
-              T* dst = pq ? Ri : Rr;
-              dst[(j & 15) * ld + 8 * ct + cq] = acc[a][b][i];
-            }
-          }
+          for (int i = 0; i < 4; ++i) rp[i][8 * ct] = acc[a][b][i];
         }
       }
     }
@@ -1296,7 +1297,7 @@ static hipError_t launch_factor_mfma_t(hdsw_ctx* c, int step, int middle) {
   while (ld % 64 != 16 && ld % 64 != 48) ld += 16;   // conflict-free operand reads
   const size_t lds = (size_t)16 * g.nP * sizeof(cpx<T>) + (size_t)4 * 16 * ld * sizeof(T) +
                      (size_t)(2 * g.nP + 2) * sizeof(int) + (16 + 256) * sizeof(cpx<T>) +
-                     16 * sizeof(unsigned);
+                     16 * sizeof(unsigned) + (size_t)(64 + g.nP) * sizeof(T);
   const size_t xs = (size_t)g.K * g.nP * g.nP;
   hipLaunchKernelGGL((k_factor_mfma<T, RA, CB>), dim3(c->nops, 2), dim3(512), lds, c->stream,
                      (cpx<T>*)c->d_X, xs, (const cpx<T>*)c->d_coefT, c->coef_stride, c->gd,
