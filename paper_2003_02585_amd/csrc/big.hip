@@ -591,6 +591,7 @@ __global__ __launch_bounds__(1024) void k_gj_panel_reg(cpx<T>* X, long long sz, 
       if (i < n && c < nbr) pr[s][c] = A[(long long)(j0 + c) * n + i];
     }
   }
+  int anybad = 0;                              // thread 0: a zero or NaN pivot
   // the pivot loop is unrolled: column q of the panel is a static register
   // index in every step
 #pragma unroll
@@ -626,22 +627,20 @@ __global__ __launch_bounds__(1024) void k_gj_panel_reg(cpx<T>* X, long long sz, 
     }
     if (lane == 0) okey[slot][wave] = wk;
     lds_barrier();
+    // the sixteen offers' keys: they are distinct (each carries its row)
+    // and the best is positive (a candidate exists for every column: n - j0
+    // - q rows), so the pivot row p is the one in the largest key, found by
+    // a max tree, and the wave that offered it is the one holding row p
+    // (row i lives in thread i mod 1024)
     const uint4* ok4 = reinterpret_cast<const uint4*>(okey[slot]);
-    unsigned best = 0u;
-    int bw = 0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const uint4 kv = ok4[v];
-      if (kv.x > best) { best = kv.x; bw = 4 * v; }
-      if (kv.y > best) { best = kv.y; bw = 4 * v + 1; }
-      if (kv.z > best) { best = kv.z; bw = 4 * v + 2; }
-      if (kv.w > best) { best = kv.w; bw = 4 * v + 3; }
-    }
-    // a candidate exists for every column (n - j0 - q rows), so best > 0
-    const int p = 8191 - (int)(best & 8191u);
+    const uint4 k0 = ok4[0], k1 = ok4[1], k2 = ok4[2], k3 = ok4[3];
+    const unsigned best =
+        max(max(max(max(k0.x, k0.y), max(k0.z, k0.w)), max(max(k1.x, k1.y), max(k1.z, k1.w))),
+            max(max(max(k2.x, k2.y), max(k2.z, k2.w)), max(max(k3.x, k3.y), max(k3.z, k3.w))));
+    const int p = 8191 - (int)(best & 8191u), bw = (p & 1023) >> 6;
     const cpx<T>* ph = offer[slot][bw];
     if (tid == 0) {
-      if (obad[slot][bw]) atomicExch(flag, 1);
+      anybad |= obad[slot][bw];
       prow_of[q] = p;
     }
 #pragma unroll
@@ -670,6 +669,7 @@ __global__ __launch_bounds__(1024) void k_gj_panel_reg(cpx<T>* X, long long sz, 
       }
     }
   }
+  if (tid == 0 && anybad) atomicExch(flag, 1);
   lds_barrier();
   // the interchanges: position j0 + q swaps with the position its pivot
   // row holds at that point; only the rows of the swaps move
