@@ -71,6 +71,10 @@ DDM_CASES = [
     (256, 4, (32, 32), None, 1), # partition of the largest serving grids
     (256, 4, (32, 32), 1.5, 2),
     (416, 8, (2, 2), None, 1),   # n = 224: complex128 block solve on 4 waves
+    (192, 8, (2, 2), None, 1),   # n = 112: four row tiles per wave pair in the
+                                 # complex64 factor on the matrix cores; complex128
+                                 # through the global-memory Gauss-Jordan
+    (256, 8, (2, 2), 1.5, 1),    # n = 144: five row tiles, the last one past n
 ]
 
 
@@ -96,6 +100,8 @@ def test_fp64_ddm_matches_oracle(H, N, W, P, layer, rounds):
 @pytest.mark.parametrize("N,W,P,layer,rounds", DDM_CASES[:4] + [
     (384, 8, (2, 2), 1.5, 1),    # n = 208: 13 row tiles, 8-tile waves, odd split
     (56, 5, (2, 7), 1.5, 1),     # ragged
+    (192, 8, (2, 2), None, 1),   # n = 112 and 144: the factor on the matrix cores
+    (256, 8, (2, 2), 1.5, 1),    # with four and five row tiles per wave pair
 ])
 def test_mixed_ddm_close_to_oracle(H, N, W, P, layer, rounds):
     c = _case(N, W, P, layer, nrhs=2)
